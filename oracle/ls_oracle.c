@@ -65,14 +65,15 @@ static void nadd(nsum *acc, double x) {
 static double nval(const nsum *acc) { return acc->s + acc->c; }
 
 /* The frequency f_k = f0 + k*df as an unevaluated pair hi + lo (exact to
- * ~2^-106 relative).  Returns 1 when f_k is exactly zero. */
+ * ~2^-106 relative).  Returns 1 for the zero frequency, read as the frequency
+ * whose binary64 value fl(f0 + fl(k*df)) is zero (f0 == -fl(k*df)). */
 static int freq_dd(double f0, double df, int64_t k, double *hi, double *lo) {
   double p, e1, s, e2;
   two_prod((double)k, df, &p, &e1);
   two_sum(f0, p, &s, &e2);
   *hi = s;
   *lo = e1 + e2;
-  return (s == 0.0 && *lo == 0.0);
+  return (s == 0.0);
 }
 
 /* Phase of f*t in cycles, reduced to [-1/2, 1/2).  f is the pair (fh, fl). */
