@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the NUFFT Lomb-Scargle hot path on one MI355X.
+
+A step is one whole periodogram of the single large light curve (N_d = 1e6
+points over 3650 days with seasonal gaps, N_f = 1.2e7 frequencies, FP64,
+eps = 1e-9): statistics, binning, both spreads, the three-pass FFT of the
+three grids, deconvolution, crop and power.  Inputs are resident in HBM
+before the timed region; the plan (twiddles, kernel transform) is cached from
+the warm-up, as a NUFFT plan is.  Prints ONE JSON line.
+
+Also reported (in "extra"): the FP32 precision form on the same curve, and the
+error of both against the oracle on the sampled frequencies used for the CPU
+baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N_d·N_f-equiv sums/s FP64 vs FP32-batched at stated error; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nd", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2409_08090_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, fn), "rb") as f:
+                h.update(fn.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def active_fraction(t, df, geo, plan, tau):
+    """Fraction of grid rows the spread writes (rows within half a kernel width
+    of a point), from the host copy of t; used in the algorithmic byte model."""
+    n = plan["n"]
+    rows = plan["len"][0] if plan["npass"] > 1 else 1
+    S1 = n // rows
+    u = n * np.mod(geo * df * (t - tau), 1.0)
+    hw = plan["width"] / 2 + 1
+    active = np.zeros(rows, bool)
+    for off in (-hw, 0.0, hw):
+        active[(np.floor(np.mod(u + off, n) / S1)).astype(np.int64)] = True
+    return active.mean()
+
+
+def byte_model(c, plan, csize):
+    """Algorithmic bytes per launch of each stage (see the design notes):
+    inputs read once, spread writes of the active rows, every FFT pass reading
+    and writing each grid once (the first pass reads only active rows), the
+    last pass writing only the power and reading the kernel-transform table."""
+    n, nd, nf = plan["n"], c.nd, c.nf
+    tau = c.t.min()
+    rf = active_fraction(c.t, c.df, 1, plan, tau)
+    r2 = active_fraction(c.t, c.df, 2, plan, tau)
+    ng = 3
+    m = {
+        "stats": 24.0 * nd,
+        "bin_sort": 8.0 * nd + 4.0 * (n // plan["bin"] + 1),
+        "spread_f": 24.0 * nd + 2 * rf * n * csize,
+        "spread_2f": 16.0 * nd + r2 * n * csize,
+        "fft_pass_0": (2 * rf + r2) * n * csize + ng * n * csize,
+        "fft_pass_1": 2.0 * ng * n * csize,
+        "fft_pass_2": 2.0 * ng * n * csize,
+        "fft_last_power": ng * n * csize + 8.0 * nf + 8.0 * (nf // 2 + 1),
+    }
+    return m, rf, r2
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by frequency band across GPUs, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2409_08090_amd import mils, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    c = workloads.single_large(seed=1, nd=args.nd)
+    eps = 1e-9
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    t, y, dy = to(c.t), to(c.y), to(c.dy)
+    power = torch.empty(c.nf, dtype=torch.float64, device=dev)
+    ctx = mils.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step(prec="fp64", e=eps, out=power, sync=False):
+        mils.periodogram(t, y, dy, c.f0, c.df, c.nf, eps=e, precision=prec, out=out,
+                         stream=stream, ctx=ctx, sync=sync)
+
+    for _ in range(max(1, args.warmup)):
+        step(sync=True)
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check(mils.load().mils_context_status(ctx.handle))
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    sums = float(c.nd) * float(c.nf)
+    value = sums / (ms_per_step * 1e-3)
+
+    plan = mils.plan_info(c.nd, c.nf, eps, "fp64", c.f0, c.df)
+    bytes_model, rf, r2 = byte_model(c, plan, 16)
+    stages = {}
+    for name, (ms, n) in prof.items():
+        avg = ms / n
+        b = bytes_model.get(name, 0.0)
+        stages[name] = {"avg_ms": round(avg, 5), "alg_bytes": b,
+                        "alg_GBs": round(b / (avg * 1e-3) / 1e9, 1)}
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms = prof[dom][0] / prof[dom][1]
+    achieved = bytes_model[dom] / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic_single_large_fp64.json")
+    if os.path.exists(tpath):
+        try:
+            rec = json.load(open(tpath))
+            if rec.get("kernel_hash") == kernel_source_hash() and dom in rec.get("bytes", {}):
+                traffic = rec["bytes"][dom]
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom}
+    whole_path_bytes = sum(bytes_model[k] for k in prof)
+    extra = {"stages": stages, "active_rows": {"f": round(rf, 4), "2f": round(r2, 4)},
+             "plan": plan, "whole_path_alg_GBs": round(whole_path_bytes / (ms_per_step * 1e-3) / 1e9, 1)}
+
+    # FP32 precision form on the same curve
+    if not args.no_extra:
+        p32 = torch.empty_like(power)
+        for _ in range(2):
+            step("fp32", 1e-5, p32, sync=True)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for _ in range(args.steps):
+            step("fp32", 1e-5, p32)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        ms32 = (a1 - a0) * 1e3 / args.steps
+        extra["fp32_form"] = {"ms_per_step": round(ms32, 4), "value": sums / (ms32 * 1e-3),
+                              "eps": 1e-5}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(2)
+        # calibrate the sample size on a few frequencies, then time the sample
+        k0 = rng.integers(0, c.nf, 8)
+        s0 = time.perf_counter()
+        oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k0)
+        per = (time.perf_counter() - s0) / k0.size
+        nk = int(max(16, min(4000, args.cpu_seconds / max(per, 1e-6))))
+        top = np.argsort(power.cpu().numpy())[-20:]
+        ks = np.unique(np.concatenate([rng.integers(0, c.nf, nk), top]))
+        s1 = time.perf_counter()
+        ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=ks)
+        el = time.perf_counter() - s1
+        cpu = {"value": float(c.nd) * ks.size / el, "unit": "sums/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{ks.size} frequencies of the N_d=1e6, N_f=1.2e7 FP64 curve "
+                         f"(random k plus the 20 strongest GPU peaks), {el:.1f} s"}
+        p64 = power.cpu().numpy()
+        extra["error_fp64"] = float(np.max(np.abs(p64[ks] - ref)) / np.max(np.abs(ref)))
+        if "fp32_form" in extra:
+            e32 = float(np.max(np.abs(p32.cpu().numpy()[ks] - ref)) / np.max(np.abs(ref)))
+            extra["fp32_form"]["error_vs_oracle"] = e32
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sums/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "single large light curve FP64: N_d=1e6 times over 3650 d with "
+                               "120-day gaps, N_f=1.2e7, df=1/18250, eps=1e-9",
+                   "nd": c.nd, "nf": c.nf, "eps": eps, "precision": "fp64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

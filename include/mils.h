@@ -1,0 +1,201 @@
+/*
+ * mils.h -- C ABI of libmils, an MI355X (gfx950) implementation of the NUFFT
+ * Lomb-Scargle periodogram of the nifty-ls paper.
+ *
+ * Method (nifty-ls paper, Sec. 1): the weighted trigonometric sums of Eq. 1,
+ *     C_k + i S_k = sum_j h_j exp(+i 2 pi f_k t_j),   f_k = f0 + k df,
+ * are a type-1 (non-uniform to uniform) NUFFT, Eq. 2.  They are evaluated by
+ * spreading the points onto an upsampled uniform grid with the "exponential of
+ * semicircle" kernel, taking an FFT, and dividing by the kernel's Fourier
+ * transform (the diagonal rescaling), with kernel width and grid size chosen
+ * from the user tolerance eps.  A periodogram needs the sums at f for the
+ * weighted data and the weights, and at 2f for the weights; the power is then
+ * assembled per frequency.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments marked (device) are device pointers (for example
+ *     torch.Tensor.data_ptr() of a CUDA/HIP tensor) owned by the caller; the
+ *     library never frees or retains them after the call has completed on its
+ *     stream.  Arrays marked (host) are ordinary host memory.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  All device
+ *     work of a call is enqueued on that stream.
+ *   - Argument checks (null pointers, sizes, ranges, enum values) happen on
+ *     the host before any device work; a failed check returns
+ *     MILS_ERR_INVALID_ARG and enqueues nothing.  Content checks (non-finite
+ *     values, dy <= 0, constant data) happen on the device and are reported
+ *     by the synchronous call, or by mils_context_status after an _async call;
+ *     the output is then unspecified.
+ *   - No C++ exception crosses this interface.  Every call returns a status
+ *     code; mils_last_error gives a human-readable message for the context.
+ *   - One context may be used by one host thread at a time.  Calls on one
+ *     context share its workspace, so they must not overlap on the device:
+ *     enqueue them on one stream, or use one context per stream.
+ */
+#ifndef MILS_H
+#define MILS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MILS_VERSION 10000 /* 1.0.0 */
+
+/* Status codes. */
+enum {
+  MILS_OK = 0,
+  MILS_ERR_INVALID_ARG = -1, /* bad argument, or invalid values found on device */
+  MILS_ERR_DEGENERATE = -2,  /* the data are constant: the reference chi^2 is 0 */
+  MILS_ERR_OOM = -3,         /* device allocation failed or the HBM budget is exceeded */
+  MILS_ERR_DEVICE = -4,      /* a HIP runtime error; the context is unusable */
+  MILS_ERR_UNSUPPORTED = -5, /* eps outside the range of the precision, size too large */
+  MILS_ERR_BUSY = -6,        /* server queue full */
+  MILS_ERR_CANCELLED = -7,   /* server request cancelled (server shut down) */
+  MILS_ERR_TIMEOUT = -8      /* server wait timed out */
+};
+
+/* Arithmetic of the spread and FFT.  Rescaling to grid coordinates, the f0
+ * phase shift, deconvolution and the power assembly are FP64 in both. */
+enum { MILS_FP64 = 0, MILS_FP32 = 1 };
+
+/* Normalisation of the power; chi2_ref is the weighted residual of the model
+ * without the sinusoid (the best constant with MILS_FIT_MEAN, else zero) and
+ * chi2 the residual of the best fit including the sinusoid at f.
+ *   STANDARD (chi2_ref - chi2) / chi2_ref
+ *   MODEL    (chi2_ref - chi2) / chi2
+ *   LOG      ln(chi2_ref / chi2)
+ *   PSD      (chi2_ref - chi2) / 2, with weights 1/dy^2 (1 when dy is NULL) */
+enum { MILS_NORM_STANDARD = 0, MILS_NORM_MODEL = 1, MILS_NORM_LOG = 2, MILS_NORM_PSD = 3 };
+
+/* Flags. */
+enum {
+  MILS_CENTER_DATA = 1, /* subtract the weighted mean of y before the sums */
+  MILS_FIT_MEAN = 2     /* include a constant offset in the fitted model ("floating mean") */
+};
+
+typedef struct mils_context mils_context;
+
+/* Periodogram parameters.  The frequency grid is f_k = f0 + k df, k = 0..nf-1
+ * (the paper's Eq. 1 writes k = 0..N_f; N_f values are computed here). */
+typedef struct {
+  double f0;             /* first frequency (cycles per unit of t), finite */
+  double df;             /* frequency step, finite and > 0 */
+  int64_t nf;            /* number of frequencies, 1 <= nf <= 2^28 */
+  double eps;            /* requested NUFFT tolerance: FP64 [1e-14, 1e-2], FP32 [1e-6, 1e-2] */
+  int32_t precision;     /* MILS_FP64 or MILS_FP32 */
+  int32_t normalization; /* MILS_NORM_* */
+  uint32_t flags;        /* MILS_CENTER_DATA | MILS_FIT_MEAN (the default) */
+} mils_params;
+
+/* What the planner chose for a problem (host-only query). */
+typedef struct {
+  double sigma;        /* upsampling factor n / nf */
+  int32_t width;       /* kernel width w in fine-grid cells */
+  double beta;         /* exponential-of-semicircle shape parameter */
+  int64_t n;           /* fine grid size */
+  int32_t npass;       /* FFT passes through HBM (1 = the whole grid stays on chip) */
+  int32_t len[4];      /* FFT length of each pass; n = len[0]*...*len[npass-1] */
+  int32_t tile;        /* spreading tile, in cells */
+  int32_t bin;         /* point-binning granularity, in cells */
+  uint64_t workspace_bytes; /* device workspace the call needs */
+} mils_plan_desc;
+
+/* Library version (MILS_VERSION of the build). */
+int mils_version(void);
+
+/* Static description of a status code. */
+const char *mils_status_str(int status);
+
+/* Last error message recorded on the context ("" if none).  ctx may be NULL,
+ * which returns the message of the last failed mils_context_create. */
+const char *mils_last_error(const mils_context *ctx);
+
+/* Create a context on HIP device `device`.  device = -1 creates a host-only
+ * context that can plan and validate but not compute (every compute call
+ * returns MILS_ERR_DEVICE).  hbm_budget_bytes bounds the workspace the
+ * context may hold (0 = no bound).  *out receives the context. */
+int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context **out);
+
+/* Release the context and its device workspace (synchronises its device). */
+int mils_context_destroy(mils_context *ctx);
+
+/* Fill *out with the plan for a periodogram of nd points with parameters p.
+ * Host-only; valid on a host-only context. */
+int mils_plan_info(mils_context *ctx, int64_t nd, const mils_params *p, mils_plan_desc *out);
+
+/* Check the arguments of mils_periodogram without touching the device;
+ * returns MILS_OK or the code mils_periodogram would return before launching. */
+int mils_check_periodogram_args(const double *t, const double *y, int64_t nd,
+                                const mils_params *p, const double *power);
+
+/*
+ * Raw trigonometric sums (Eq. 1 / Eq. 2 of the paper):
+ *   out[2k] + i out[2k+1] = sum_j h_j exp(+i 2 pi (f0 + k df) t_j),  k = 0..nf-1,
+ * to relative accuracy ~eps (in the norm sum_j |h_j|).  t, h: nd doubles
+ * (device); out: 2*nf doubles (device), interleaved re/im.  The time origin is
+ * not shifted.  Synchronous: returns after the result is complete.
+ */
+int mils_trig_sums(mils_context *ctx, const double *t, const double *h, int64_t nd,
+                   double f0, double df, int64_t nf, double eps, int32_t precision,
+                   double *out, void *hip_stream);
+
+/*
+ * Lomb-Scargle periodogram of one series (the method of the paper, Sec. 1):
+ * t, y: nd doubles (device); dy: nd doubles (device) or NULL for unit weights;
+ * power: p->nf doubles (device), written with the power at f0 + k df.
+ * The power is exactly 0 where fl(f0 + fl(k df)) == 0.  Where the fit is
+ * singular (e.g. evenly spaced t at a multiple of the Nyquist frequency) the
+ * power is 0.  Synchronous: returns after the result is complete, with the
+ * status of the device-side content checks.
+ */
+int mils_periodogram(mils_context *ctx, const double *t, const double *y, const double *dy,
+                     int64_t nd, const mils_params *p, double *power, void *hip_stream);
+
+/* As mils_periodogram, but returns once the work is enqueued on hip_stream.
+ * The device-side status is read by mils_context_status. */
+int mils_periodogram_async(mils_context *ctx, const double *t, const double *y,
+                           const double *dy, int64_t nd, const mils_params *p, double *power,
+                           void *hip_stream);
+
+/* Wait for the last call enqueued on the context and return its device-side
+ * status (MILS_OK, MILS_ERR_INVALID_ARG or MILS_ERR_DEGENERATE). */
+int mils_context_status(mils_context *ctx);
+
+/*
+ * Batched periodograms: ncurves independent series in CSR layout.  Curve c
+ * has points nd_off[c] .. nd_off[c+1]-1 of t, y, dy and writes power
+ * nf_off[c] .. nf_off[c+1]-1 at frequencies f0[c] + k df[c].  nd_off, nf_off
+ * (ncurves+1 int64), f0, df (ncurves doubles) are HOST arrays; t, y, dy, power
+ * are device arrays (dy may be NULL).  common supplies eps, precision,
+ * normalization and flags (its f0, df, nf are ignored).  status_per_curve
+ * (host, nullable, ncurves int32) receives each curve's device-side status.
+ * Synchronous.
+ */
+int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd_off,
+                           const double *t, const double *y, const double *dy,
+                           const int64_t *nf_off, const double *f0, const double *df,
+                           const mils_params *common, double *power,
+                           int32_t *status_per_curve, void *hip_stream);
+
+/*
+ * Per-stage timing of the single-series path (measurement support).  While
+ * enabled, every call records a pair of HIP events around each stage of the
+ * path on the call's stream.  Stages: 0 statistics, 1 binning / sort,
+ * 2 spread (geometry f), 3 spread (geometry 2f), 4-6 FFT passes through HBM
+ * (first pass pruned), 7 last FFT pass fused with deconvolution, crop and
+ * power.  mils_profile_enable(ctx, 1) clears the accumulators.
+ * mils_profile_read waits for the recorded events and adds, per stage, the
+ * total elapsed milliseconds and the number of timed launches to ms_total[s]
+ * and launches[s] (host arrays of MILS_NUM_STAGES entries), then clears them.
+ */
+enum { MILS_NUM_STAGES = 8 };
+int mils_profile_enable(mils_context *ctx, int enable);
+const char *mils_profile_stage_name(int stage);
+int mils_profile_read(mils_context *ctx, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MILS_H */

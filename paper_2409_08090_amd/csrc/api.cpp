@@ -1,0 +1,498 @@
+// api.cpp -- the C ABI of libmils (include/mils.h): contexts, argument
+// validation, plan cache, workspace and the synchronous / asynchronous
+// periodogram and trig-sum calls.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mils.h"
+#include "kernels.h"
+#include "mils_internal.h"
+#include "plan.h"
+
+using namespace mils;
+
+namespace {
+
+struct PlanEntry {
+  Plan plan;
+  void* tw = nullptr;            // twiddles (FP64 or FP32 pairs)
+  double* inv_phihat = nullptr;  // K + 1 doubles
+  size_t bytes = 0;
+};
+
+using PlanKey = std::tuple<int64_t, double, int, int, double>;
+
+std::mutex g_err_mu;
+std::string g_create_err;
+
+void host_dd_sum(double a, double b, double* s, double* e) {
+  double x = a + b;
+  double bb = x - a;
+  *e = (a - (x - bb)) + (b - bb);
+  *s = x;
+}
+
+}  // namespace
+
+struct mils_context {
+  int device = -1;
+  uint64_t budget = 0;
+  std::string err;
+  bool poisoned = false;
+  std::map<PlanKey, PlanEntry> plans;
+  size_t plan_bytes = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* host_status = nullptr;  // pinned
+  DevStats* last_stats = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool have_pending = false;
+  // per-stage event timing
+  bool prof = false;
+  hipEvent_t prof_begin[kNumStages] = {};
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_recs;
+  std::vector<hipEvent_t> prof_pool;
+};
+
+namespace {
+
+int fail(mils_context* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(mils_context* ctx, hipError_t e, const char* where) {
+  if (ctx) {
+    ctx->poisoned = true;
+    ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return MILS_ERR_DEVICE;
+}
+
+int check_params(const mils_params* p) {
+  if (!p) return MILS_ERR_INVALID_ARG;
+  if (!(std::isfinite(p->f0)) || !(std::isfinite(p->df)) || !(p->df > 0.0))
+    return MILS_ERR_INVALID_ARG;
+  if (p->nf < 1) return MILS_ERR_INVALID_ARG;
+  if (p->nf > ((int64_t)1 << 28)) return MILS_ERR_UNSUPPORTED;
+  if (p->precision != MILS_FP64 && p->precision != MILS_FP32) return MILS_ERR_INVALID_ARG;
+  if (p->normalization < 0 || p->normalization > 3) return MILS_ERR_INVALID_ARG;
+  if (p->flags & ~(uint32_t)(MILS_CENTER_DATA | MILS_FIT_MEAN)) return MILS_ERR_INVALID_ARG;
+  if (!std::isfinite(p->eps) || !(p->eps > 0.0)) return MILS_ERR_INVALID_ARG;
+  const double lo = p->precision == MILS_FP64 ? 1e-14 : 1e-6;
+  if (p->eps < lo || p->eps > 1e-2) return MILS_ERR_UNSUPPORTED;
+  if (!std::isfinite(p->f0 + (double)(p->nf - 1) * p->df)) return MILS_ERR_INVALID_ARG;
+  return MILS_OK;
+}
+
+int check_nd(int64_t nd) {
+  if (nd < 1 || nd > (int64_t)0x7fffffff) return MILS_ERR_INVALID_ARG;
+  return MILS_OK;
+}
+
+int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEntry** out,
+             bool upload) {
+  PlanKey key{nf, eps, prec, G, 0.0};
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end() && (!upload || it->second.tw)) {
+    *out = &it->second;
+    return MILS_OK;
+  }
+  PlanEntry e;
+  std::string err;
+  PlanRequest r{nf, eps, prec, G};
+  if (!make_plan(r, &e.plan, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
+  std::vector<double> tw;
+  make_twiddles(&e.plan, &tw);
+  if (upload) {
+    const size_t twbytes = prec == 1 ? tw.size() * sizeof(float) : tw.size() * sizeof(double);
+    const size_t phbytes = sizeof(double) * (e.plan.K + 1);
+    std::vector<double> z, gphi;
+    phihat_nodes(e.plan, &z, &gphi);
+    const size_t nbytes = sizeof(double) * 2 * z.size();
+    e.bytes = twbytes + phbytes + nbytes;
+    if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + e.bytes > ctx->budget)
+      return fail(ctx, MILS_ERR_OOM, "plan tables exceed the HBM budget");
+    char* buf = nullptr;
+    hipError_t he = hipMalloc(&buf, twbytes + phbytes + nbytes + 512);
+    if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "hipMalloc of plan tables failed");
+    e.inv_phihat = reinterpret_cast<double*>(buf);
+    e.tw = buf + ((phbytes + 255) & ~(size_t)255);
+    double* nodes = reinterpret_cast<double*>(
+        reinterpret_cast<char*>(e.tw) + ((twbytes + 255) & ~(size_t)255));
+    if (prec == 1) {
+      std::vector<float> f(tw.begin(), tw.end());
+      he = hipMemcpy(e.tw, f.data(), twbytes, hipMemcpyHostToDevice);
+    } else {
+      he = hipMemcpy(e.tw, tw.data(), twbytes, hipMemcpyHostToDevice);
+    }
+    if (he != hipSuccess) return hip_fail(ctx, he, "plan upload");
+    std::vector<double> zn(z);
+    zn.insert(zn.end(), gphi.begin(), gphi.end());
+    he = hipMemcpy(nodes, zn.data(), nbytes, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return hip_fail(ctx, he, "plan upload");
+    he = launch_phihat(e.inv_phihat, e.plan.K, (double)e.plan.w, (double)e.plan.n, nodes,
+                       nodes + z.size(), (int)z.size(), nullptr);
+    if (he == hipSuccess) he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "phihat kernel");
+    ctx->plan_bytes += e.bytes;
+  }
+  auto& slot = ctx->plans[key];
+  if (slot.tw) {
+    (void)hipFree(reinterpret_cast<char*>(slot.inv_phihat));
+    ctx->plan_bytes -= slot.bytes;
+  }
+  slot = e;
+  *out = &slot;
+  return MILS_OK;
+}
+
+int ensure_workspace(mils_context* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return MILS_OK;
+  if (ctx->budget && ctx->plan_bytes + bytes > ctx->budget)
+    return fail(ctx, MILS_ERR_OOM, "workspace exceeds the HBM budget");
+  if (ctx->ws) {
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "workspace resize");
+    (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  char* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, MILS_ERR_OOM, "hipMalloc of the workspace failed");
+  }
+  ctx->ws = p;
+  ctx->ws_bytes = bytes;
+  // the statistics block holds the self-resetting reduction counter
+  hipError_t he = hipMemset(p, 0, 4096);
+  if (he != hipSuccess) return hip_fail(ctx, he, "workspace init");
+  return MILS_OK;
+}
+
+hipEvent_t prof_event(mils_context* ctx) {
+  if (!ctx->prof_pool.empty()) {
+    hipEvent_t e = ctx->prof_pool.back();
+    ctx->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void prof_hook(void* ud, int stage, int begin, hipStream_t s) {
+  mils_context* ctx = static_cast<mils_context*>(ud);
+  hipEvent_t e = prof_event(ctx);
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  if (begin) {
+    ctx->prof_begin[stage] = e;
+  } else if (ctx->prof_begin[stage]) {
+    ctx->prof_recs.emplace_back(stage, ctx->prof_begin[stage], e);
+    ctx->prof_begin[stage] = nullptr;
+  } else {
+    ctx->prof_pool.push_back(e);
+  }
+}
+
+// Common body of the single-series calls.
+int run_single(mils_context* ctx, const double* t, const double* y, const double* dy,
+               const double* h, int64_t nd, const mils_params* p, double* power, double* sums,
+               hipStream_t stream, bool sync) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
+  const bool pg = (y != nullptr);
+  const int G = pg ? 3 : 1;
+  PlanEntry* pe = nullptr;
+  int rc = get_plan(ctx, p->nf, p->eps, p->precision, G, &pe, true);
+  if (rc != MILS_OK) return rc;
+  const Plan& plan = pe->plan;
+  const size_t need = layout_work(plan, nd, G, nullptr, nullptr);
+  rc = ensure_workspace(ctx, need);
+  if (rc != MILS_OK) return rc;
+  Work w{};
+  layout_work(plan, nd, G, ctx->ws, &w);
+  w.tw = pe->tw;
+  w.inv_phihat = pe->inv_phihat;
+
+  CallArgs a{};
+  a.t = t;
+  a.y = y;
+  a.dy = dy;
+  a.h = h;
+  a.nd = nd;
+  a.f0 = p->f0;
+  a.df = p->df;
+  // f_c = f0 + K df as a double-double (K df is exact as a two-product)
+  {
+    const double Kd = (double)plan.K;
+    double prod = Kd * p->df;
+    double perr = std::fma(Kd, p->df, -prod);
+    double s, e;
+    host_dd_sum(p->f0, prod, &s, &e);
+    a.fch = s;
+    a.fcl = e + perr;
+  }
+  // output index of the zero frequency: the k whose binary64 frequency
+  // fl(f0 + fl(k df)) is zero
+  a.kzero = -1;
+  {
+    double kq = std::nearbyint(-p->f0 / p->df);
+    for (double kk = kq - 1; kk <= kq + 1; kk += 1.0)
+      if (kk >= 0.0 && kk < (double)p->nf && kk * p->df == -p->f0) a.kzero = (int64_t)kk;
+  }
+  a.norm = p->normalization;
+  a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
+  a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.periodogram = pg ? 1 : 0;
+  a.power = power;
+  a.sums = sums;
+  StageHook hook{prof_hook, ctx};
+  he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr);
+  if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+  ctx->last_stats = w.stats;
+  ctx->last_stream = stream;
+  ctx->have_pending = true;
+  if (!sync) return MILS_OK;
+  return mils_context_status(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mils_version(void) { return MILS_VERSION; }
+
+const char* mils_status_str(int s) {
+  switch (s) {
+    case MILS_OK: return "ok";
+    case MILS_ERR_INVALID_ARG: return "invalid argument";
+    case MILS_ERR_DEGENERATE: return "degenerate input (constant data)";
+    case MILS_ERR_OOM: return "out of device memory or HBM budget";
+    case MILS_ERR_DEVICE: return "device error";
+    case MILS_ERR_UNSUPPORTED: return "unsupported parameters";
+    case MILS_ERR_BUSY: return "busy";
+    case MILS_ERR_CANCELLED: return "cancelled";
+    case MILS_ERR_TIMEOUT: return "timed out";
+    default: return "unknown status";
+  }
+}
+
+const char* mils_last_error(const mils_context* ctx) {
+  if (!ctx) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_create_err.c_str();
+  }
+  return ctx->err.c_str();
+}
+
+int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** out) {
+  if (!out) return MILS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (device < -1) return MILS_ERR_INVALID_ARG;
+  mils_context* c = new (std::nothrow) mils_context();
+  if (!c) return MILS_ERR_OOM;
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (device >= 0) {
+    int count = 0;
+    hipError_t he = hipGetDeviceCount(&count);
+    if (he != hipSuccess || device >= count) {
+      std::lock_guard<std::mutex> lk(g_err_mu);
+      g_create_err = "no such HIP device";
+      delete c;
+      return MILS_ERR_DEVICE;
+    }
+    he = hipSetDevice(device);
+    if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), 64);
+    if (he != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_err_mu);
+      g_create_err = std::string("context init: ") + hipGetErrorString(he);
+      delete c;
+      return MILS_ERR_DEVICE;
+    }
+  }
+  *out = c;
+  return MILS_OK;
+}
+
+int mils_context_destroy(mils_context* ctx) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->plans)
+      if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->host_status) (void)hipHostFree(ctx->host_status);
+    for (auto& r : ctx->prof_recs) {
+      (void)hipEventDestroy(std::get<1>(r));
+      (void)hipEventDestroy(std::get<2>(r));
+    }
+    for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
+  }
+  delete ctx;
+  return MILS_OK;
+}
+
+int mils_check_periodogram_args(const double* t, const double* y, int64_t nd,
+                                const mils_params* p, const double* power) {
+  if (!t || !y || !power) return MILS_ERR_INVALID_ARG;
+  int rc = check_nd(nd);
+  if (rc != MILS_OK) return rc;
+  return check_params(p);
+}
+
+int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_plan_desc* out) {
+  if (!ctx || !out) return MILS_ERR_INVALID_ARG;
+  int rc = check_nd(nd);
+  if (rc == MILS_OK) rc = check_params(p);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid plan query");
+  PlanEntry* pe = nullptr;
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false);
+  if (rc != MILS_OK) return rc;
+  const Plan& pl = pe->plan;
+  std::memset(out, 0, sizeof(*out));
+  out->sigma = pl.sigma;
+  out->width = pl.w;
+  out->beta = pl.beta;
+  out->n = pl.n;
+  out->npass = pl.npass;
+  for (int i = 0; i < pl.npass; ++i) out->len[i] = pl.pass[i].L;
+  out->tile = pl.T;
+  out->bin = pl.Tb;
+  out->workspace_bytes = layout_work(pl, nd, 3, nullptr, nullptr);
+  return MILS_OK;
+}
+
+int mils_trig_sums(mils_context* ctx, const double* t, const double* h, int64_t nd, double f0,
+                   double df, int64_t nf, double eps, int32_t precision, double* out,
+                   void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (!t || !h || !out) return fail(ctx, MILS_ERR_INVALID_ARG, "null pointer argument");
+  int rc = check_nd(nd);
+  if (rc != MILS_OK) return fail(ctx, rc, "nd out of range");
+  mils_params p{f0, df, nf, eps, precision, 0, 0};
+  rc = check_params(&p);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid parameters");
+  return run_single(ctx, t, nullptr, nullptr, h, nd, &p, nullptr, out,
+                    reinterpret_cast<hipStream_t>(hip_stream), true);
+}
+
+int mils_periodogram_async(mils_context* ctx, const double* t, const double* y, const double* dy,
+                           int64_t nd, const mils_params* p, double* power, void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  int rc = mils_check_periodogram_args(t, y, nd, p, power);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
+  return run_single(ctx, t, y, dy, nullptr, nd, p, power, nullptr,
+                    reinterpret_cast<hipStream_t>(hip_stream), false);
+}
+
+int mils_periodogram(mils_context* ctx, const double* t, const double* y, const double* dy,
+                     int64_t nd, const mils_params* p, double* power, void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  int rc = mils_check_periodogram_args(t, y, nd, p, power);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
+  return run_single(ctx, t, y, dy, nullptr, nd, p, power, nullptr,
+                    reinterpret_cast<hipStream_t>(hip_stream), true);
+}
+
+int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off,
+                           const double* t, const double* y, const double* dy,
+                           const int64_t* nf_off, const double* f0, const double* df,
+                           const mils_params* common, double* power, int32_t* status_per_curve,
+                           void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (ncurves < 1 || !nd_off || !nf_off || !f0 || !df || !common || !t || !y || !power)
+    return fail(ctx, MILS_ERR_INVALID_ARG, "invalid batch arguments");
+  if (nd_off[0] != 0 || nf_off[0] != 0) return fail(ctx, MILS_ERR_INVALID_ARG, "offsets must start at 0");
+  for (int64_t c = 0; c < ncurves; ++c) {
+    mils_params p = *common;
+    p.f0 = f0[c];
+    p.df = df[c];
+    p.nf = nf_off[c + 1] - nf_off[c];
+    int rc = check_nd(nd_off[c + 1] - nd_off[c]);
+    if (rc == MILS_OK) rc = check_params(&p);
+    if (rc != MILS_OK) return fail(ctx, rc, "invalid curve in batch");
+  }
+  int worst = MILS_OK;
+  for (int64_t c = 0; c < ncurves; ++c) {
+    mils_params p = *common;
+    p.f0 = f0[c];
+    p.df = df[c];
+    p.nf = nf_off[c + 1] - nf_off[c];
+    const int64_t o = nd_off[c];
+    int rc = run_single(ctx, t + o, y + o, dy ? dy + o : nullptr, nullptr, nd_off[c + 1] - o, &p,
+                        power + nf_off[c], nullptr, reinterpret_cast<hipStream_t>(hip_stream),
+                        true);
+    if (rc == MILS_ERR_DEVICE || rc == MILS_ERR_OOM || rc == MILS_ERR_UNSUPPORTED) return rc;
+    if (status_per_curve) status_per_curve[c] = rc;
+    if (rc != MILS_OK) worst = rc;
+  }
+  return worst;
+}
+
+int mils_profile_enable(mils_context* ctx, int enable) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  ctx->prof = enable != 0;
+  for (auto& r : ctx->prof_recs) {
+    ctx->prof_pool.push_back(std::get<1>(r));
+    ctx->prof_pool.push_back(std::get<2>(r));
+  }
+  ctx->prof_recs.clear();
+  return MILS_OK;
+}
+
+const char* mils_profile_stage_name(int stage) {
+  static const char* names[kNumStages] = {"stats",      "bin_sort",   "spread_f",   "spread_2f",
+                                          "fft_pass_0", "fft_pass_1", "fft_pass_2", "fft_last_power"};
+  if (stage < 0 || stage >= kNumStages) return "";
+  return names[stage];
+}
+
+int mils_profile_read(mils_context* ctx, double* ms_total, int64_t* launches) {
+  if (!ctx || !ms_total || !launches) return MILS_ERR_INVALID_ARG;
+  for (auto& r : ctx->prof_recs) {
+    hipEvent_t b = std::get<1>(r), e = std::get<2>(r);
+    hipError_t he = hipEventSynchronize(e);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, b, e);
+    if (he != hipSuccess) return hip_fail(ctx, he, "profile read");
+    ms_total[std::get<0>(r)] += ms;
+    launches[std::get<0>(r)] += 1;
+    ctx->prof_pool.push_back(b);
+    ctx->prof_pool.push_back(e);
+  }
+  ctx->prof_recs.clear();
+  return MILS_OK;
+}
+
+int mils_context_status(mils_context* ctx) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (ctx->device < 0) return MILS_OK;
+  if (!ctx->have_pending) return MILS_OK;
+  hipError_t he = hipMemcpyAsync(ctx->host_status, &ctx->last_stats->status, sizeof(int),
+                                 hipMemcpyDeviceToHost, ctx->last_stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->last_stream);
+  if (he != hipSuccess) return hip_fail(ctx, he, "status readback");
+  ctx->have_pending = false;
+  int st = *ctx->host_status;
+  if (st == -1) return fail(ctx, MILS_ERR_INVALID_ARG, "non-finite input or dy <= 0");
+  if (st == -2) return fail(ctx, MILS_ERR_DEGENERATE, "constant data: zero reference chi^2");
+  return MILS_OK;
+}
+
+}  // extern "C"

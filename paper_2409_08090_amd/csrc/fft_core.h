@@ -1,0 +1,203 @@
+// fft_core.h -- LDS-resident mixed-radix Stockham FFT building blocks
+// (sign +, unnormalised: X_m = sum_l x_l exp(+2 pi i l m / L)).
+//
+// A workgroup holds `ncol` independent columns of length L in LDS; element l
+// of column c sits at buf[c * cs + l * ls].  Each stage of radix R reads R
+// elements at stride L/R, applies the stage twiddles, takes a radix-R DFT in
+// registers and writes the outputs to their self-sorted positions (Stockham
+// autosort), so no bit reversal is needed.  All reads of a stage complete
+// (barrier) before any write, which lets the stage work in place.
+#pragma once
+
+#include "device_math.h"
+
+namespace mils {
+
+// ---- radix-R DFTs with the + sign -----------------------------------------
+template <typename T2>
+__device__ __forceinline__ void dft2(T2* a) {
+  T2 t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+
+template <typename T2>
+__device__ __forceinline__ void dft3(T2* a) {
+  using R = decltype(a[0].x);
+  const R c = (R)-0.5;
+  const R s = (R)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+  T2 b = cadd(a[1], a[2]);
+  T2 d = csub(a[1], a[2]);
+  T2 y0 = cadd(a[0], b);
+  T2 m;
+  m.x = a[0].x + c * b.x;
+  m.y = a[0].y + c * b.y;
+  T2 sd = cmuli(cscale(d, s));
+  a[0] = y0;
+  a[1] = cadd(m, sd);
+  a[2] = csub(m, sd);
+}
+
+template <typename T2>
+__device__ __forceinline__ void dft4(T2* a) {
+  T2 s02 = cadd(a[0], a[2]);
+  T2 d02 = csub(a[0], a[2]);
+  T2 s13 = cadd(a[1], a[3]);
+  T2 d13 = cmuli(csub(a[1], a[3]));
+  a[0] = cadd(s02, s13);
+  a[2] = csub(s02, s13);
+  a[1] = cadd(d02, d13);
+  a[3] = csub(d02, d13);
+}
+
+template <typename T2>
+__device__ __forceinline__ void dft5(T2* a) {
+  using R = decltype(a[0].x);
+  const R c1 = (R)0.30901699437494742410229341718282;   // cos(2 pi / 5)
+  const R s1 = (R)0.95105651629515357211643933337938;   // sin(2 pi / 5)
+  const R c2 = (R)-0.80901699437494742410229341718282;  // cos(4 pi / 5)
+  const R s2 = (R)0.58778525229247312916870595463907;   // sin(4 pi / 5)
+  T2 b1 = cadd(a[1], a[4]), d1 = csub(a[1], a[4]);
+  T2 b2 = cadd(a[2], a[3]), d2 = csub(a[2], a[3]);
+  T2 y0 = cadd(a[0], cadd(b1, b2));
+  T2 r1, r2, i1, i2;
+  r1.x = a[0].x + c1 * b1.x + c2 * b2.x;
+  r1.y = a[0].y + c1 * b1.y + c2 * b2.y;
+  r2.x = a[0].x + c2 * b1.x + c1 * b2.x;
+  r2.y = a[0].y + c2 * b1.y + c1 * b2.y;
+  i1.x = s1 * d1.x + s2 * d2.x;
+  i1.y = s1 * d1.y + s2 * d2.y;
+  i2.x = s2 * d1.x - s1 * d2.x;
+  i2.y = s2 * d1.y - s1 * d2.y;
+  i1 = cmuli(i1);
+  i2 = cmuli(i2);
+  a[0] = y0;
+  a[1] = cadd(r1, i1);
+  a[4] = csub(r1, i1);
+  a[2] = cadd(r2, i2);
+  a[3] = csub(r2, i2);
+}
+
+template <typename T2>
+__device__ __forceinline__ void dft8(T2* a) {
+  using R = decltype(a[0].x);
+  const R h = (R)0.70710678118654752440084436210485;
+  T2 e[4] = {a[0], a[2], a[4], a[6]};
+  T2 o[4] = {a[1], a[3], a[5], a[7]};
+  dft4(e);
+  dft4(o);
+  // o_k *= w8^k, w8 = exp(2 pi i / 8)
+  T2 o1, o2, o3;
+  o1.x = h * (o[1].x - o[1].y);
+  o1.y = h * (o[1].x + o[1].y);
+  o2 = cmuli(o[2]);
+  o3.x = -h * (o[3].x + o[3].y);
+  o3.y = h * (o[3].x - o[3].y);
+  a[0] = cadd(e[0], o[0]);
+  a[4] = csub(e[0], o[0]);
+  a[1] = cadd(e[1], o1);
+  a[5] = csub(e[1], o1);
+  a[2] = cadd(e[2], o2);
+  a[6] = csub(e[2], o2);
+  a[3] = cadd(e[3], o3);
+  a[7] = csub(e[3], o3);
+}
+
+template <int R, typename T2>
+__device__ __forceinline__ void dft(T2* a) {
+  if constexpr (R == 2) dft2(a);
+  else if constexpr (R == 3) dft3(a);
+  else if constexpr (R == 4) dft4(a);
+  else if constexpr (R == 5) dft5(a);
+  else if constexpr (R == 8) dft8(a);
+}
+
+// One Stockham stage of radix R over `ncol` columns of length L held in LDS.
+// Ns = product of the radices of the earlier stages.  twL[x] = exp(2 pi i x / L).
+// jfast selects the thread mapping: consecutive threads take consecutive
+// butterflies of one column (columns contiguous in LDS) or the same butterfly
+// of consecutive columns (elements of a row contiguous in LDS).
+template <int R, int MAXB, int NT, typename T2>
+__device__ __forceinline__ void stockham_stage(T2* buf, int L, int ncol, int cs, int ls, int Ns,
+                                               const T2* twL, bool jfast) {
+  const int tid = threadIdx.x;
+  const int nb = L / R;
+  const int total = nb * ncol;
+  const int twstride = L / (Ns * R);
+  T2 v[MAXB][R];
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    int idx = tid + b * NT;
+    if (idx < total) {
+      int col, j;
+      if (jfast) {
+        col = idx / nb;
+        j = idx - col * nb;
+      } else {
+        j = idx / ncol;
+        col = idx - j * ncol;
+      }
+      int k = j % Ns;
+      const T2* base = buf + col * cs;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[b][q] = base[(j + q * nb) * ls];
+      if (Ns > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[b][q] = cmul(v[b][q], twL[q * k * twstride]);
+      }
+      dft<R>(v[b]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MAXB; ++b) {
+    int idx = tid + b * NT;
+    if (idx < total) {
+      int col, j;
+      if (jfast) {
+        col = idx / nb;
+        j = idx - col * nb;
+      } else {
+        j = idx / ncol;
+        col = idx - j * ncol;
+      }
+      int k = j % Ns;
+      int dst = (j - k) * R + k;
+      T2* base = buf + col * cs;
+#pragma unroll
+      for (int q = 0; q < R; ++q) base[(dst + q * Ns) * ls] = v[b][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of all columns: runs the stages of the radix plan.
+// EMAX bounds L * ncol (it sizes the per-thread register arrays).
+template <int EMAX, int NT, typename T2>
+__device__ void lds_fft(T2* buf, int L, int ncol, int cs, int ls, const int* rad, int nrad,
+                        const T2* twL, bool jfast) {
+  int Ns = 1;
+  for (int s = 0; s < nrad; ++s) {
+    int r = rad[s];
+    switch (r) {
+      case 2:
+        stockham_stage<2, (EMAX / 2 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        break;
+      case 3:
+        stockham_stage<3, (EMAX / 3 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        break;
+      case 4:
+        stockham_stage<4, (EMAX / 4 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        break;
+      case 5:
+        stockham_stage<5, (EMAX / 5 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        break;
+      default:
+        stockham_stage<8, (EMAX / 8 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        break;
+    }
+    Ns *= r;
+  }
+}
+
+}  // namespace mils

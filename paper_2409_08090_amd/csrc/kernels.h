@@ -1,0 +1,37 @@
+// kernels.h -- host-side launchers of the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mils_internal.h"
+
+namespace mils {
+
+// Stages of the single-series path, for per-stage event timing.
+enum Stage {
+  kStageStats = 0,
+  kStageBin = 1,
+  kStageSpreadF = 2,
+  kStageSpread2F = 3,
+  kStagePass0 = 4,  // first FFT pass (pruned), then 5, 6 for later middle passes
+  kStageLast = 7,   // last FFT pass + deconvolution + power
+  kNumStages = 8
+};
+
+// Optional hook called before (begin = 1) and after (begin = 0) each stage is
+// enqueued; used to record HIP events around the stage's kernels.
+struct StageHook {
+  void (*fn)(void* ud, int stage, int begin, hipStream_t s);
+  void* ud;
+};
+
+// Enqueue the whole single-series path (statistics, binning, spread, FFT
+// passes, deconvolution and power or raw sums) on stream s.
+hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
+                       const StageHook* hook = nullptr);
+
+// 1 / phihat(m) for m = 0..K by Gauss-Legendre quadrature of the kernel.
+hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
+                         const double* gphi, int q, hipStream_t s);
+
+}  // namespace mils

@@ -1,0 +1,111 @@
+// mils_internal.h -- plan and argument structures shared by the host runtime
+// and the HIP kernels of libmils (gfx950).  Everything here is plain data
+// passed to kernels by value.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mils {
+
+constexpr int kMaxPass = 4;
+constexpr int kMaxRadixStages = 12;
+
+// One FFT pass of the multi-pass Stockham transform.  The grid of n cells is
+// viewed as [P][L][S] (P = product of the earlier lengths, S of the later
+// ones); the pass takes length-L transforms along the middle axis, multiplies
+// output k of column s by exp(+2 pi i s k / (L S)) and stores element
+// (p, k, s) at k*(P*S) + p*S + s, so that after the last pass row p holds
+// the outputs m = p + P*k.
+struct FftPass {
+  int L;
+  int C;                   // columns (S-direction) per workgroup; rows per workgroup in the last pass
+  int64_t P, S;
+  int nrad;
+  int rad[kMaxRadixStages];
+  int64_t twL_off;         // exp(2 pi i x / L), x in [0, L)
+  int64_t twlo_off;        // exp(2 pi i x / (L S)), x in [0, 2^bshift)
+  int64_t twhi_off;        // exp(2 pi i (x << bshift) / (L S))
+  int bshift;
+};
+
+// Plan of one NUFFT problem size (everything except the data).
+struct Plan {
+  int prec;                // 0 = FP64 grids, 1 = FP32 grids
+  int64_t nf;              // number of output frequencies
+  int64_t K;               // floor(nf / 2): output k <-> mode k - K
+  int64_t n;               // fine grid size
+  int w;                   // kernel width (cells)
+  double beta;             // ES shape parameter
+  double hw;               // w / 2
+  double sigma;
+  int npass;
+  FftPass pass[kMaxPass];
+  int64_t S1;              // row length of the spreading view [n / S1][S1]
+  int64_t nrows;           // n / S1
+  int T;                   // spreading tile (divides S1)
+  int Tb;                  // bin width in cells
+  int64_t nbins;           // ceil(n / Tb)
+  int D;                   // rows per workgroup of the last pass
+  int64_t tw_count;        // complex entries in the twiddle buffer
+};
+
+// Scalars produced on the device by the statistics kernel.
+struct DevStats {
+  double W;        // sum of weights
+  double mu;       // weighted mean of y
+  double M2;       // sum w (y - mu)^2
+  double tmin, tmax;
+  double tau;      // time origin subtracted before gridding
+  double ysub;     // value subtracted from y (mu when centering, else 0)
+  double Ybar;     // weighted mean of the data fed to the sums (0 when centred)
+  double YY;       // normalising variance of the power
+  int invalid;     // non-finite input or dy <= 0 seen
+  int unsorted;    // t not non-decreasing
+  int need_sort;   // points must go through the counting sort
+  int status;      // 0 ok, -1 invalid input, -2 degenerate (YY == 0)
+  unsigned int done;  // last-block counter of the reduction (self-resetting)
+  int pad[3];
+};
+
+// Per-call description of the data and output.
+struct CallArgs {
+  const double* t;
+  const double* y;    // NULL for raw trig sums
+  const double* dy;   // NULL = unit weights
+  const double* h;    // raw trig sums strengths (NULL for periodograms)
+  int64_t nd;
+  double f0, df;
+  double fch, fcl;    // f0 + K df as an unevaluated double-double
+  int64_t kzero;      // output index with f == 0 exactly, or -1
+  int norm;
+  int center, fit_mean;
+  int periodogram;    // 1: three grids + power; 0: one grid + complex sums
+  double* power;      // periodogram output
+  double* sums;       // trig sums output (interleaved re/im)
+};
+
+// Device workspace of one call, carved from one allocation.
+struct Work {
+  DevStats* stats;
+  double* partials;       // per-block partial reductions
+  int* bin_start;         // nbins + 1
+  int* bin_count;         // nbins + 1 (counting sort)
+  int* bin_cursor;        // nbins
+  int* scan_part;         // scan block sums
+  double* ts;             // sorted copies (counting sort path)
+  double* ys;
+  double* dys;
+  double* hs;
+  unsigned char* rowflag_f;   // nrows
+  unsigned char* rowflag_2f;  // nrows
+  void* grid[3];          // G grids of n complex
+  void* grid2[3];         // second buffers for passes >= 2
+  const void* tw;         // twiddles (plan-owned)
+  const double* inv_phihat;  // 1 / phihat(|m|), m = 0..K (plan-owned)
+};
+
+constexpr int kStatsBlocks = 512;
+constexpr int kThreads = 256;
+
+}  // namespace mils

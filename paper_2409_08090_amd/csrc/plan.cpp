@@ -1,0 +1,345 @@
+// plan.cpp -- the planner of libmils.
+//
+// The paper (Sec. 1) sets the kernel width and fine-grid size from the user
+// tolerance eps.  Here: for upsampling factor sigma, the exponential-of-
+// semicircle kernel of width w has aliasing error ~ exp(-pi w sqrt(1 - 1/sigma))
+// (the published heuristic of the finufft papers the method builds on), so
+// w = ceil(ln(1/eps) / (pi sqrt(1 - 1/sigma))) and beta = 0.97 pi w (1 - 1/(2 sigma)).
+// The grid size n >= sigma * nf is the cheapest 5-smooth number that factors
+// into LDS-resident passes of the Stockham FFT.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+
+namespace mils {
+
+namespace {
+
+constexpr int kTileMaxCells = 1024;   // spreading tile (LDS accumulator)
+constexpr int kMaxWidth = 16;         // widest spreading kernel
+constexpr int kLmaxPass = 1024;       // longest per-pass FFT length (twiddle LDS table)
+constexpr int kEmid64 = 4096, kEmid32 = 8192;     // elements per middle-pass workgroup
+constexpr int kElast64 = 3072, kElast32 = 6144;   // elements per last-pass workgroup
+
+std::vector<int64_t> smooth_in_range(int64_t lo, int64_t hi) {
+  std::vector<int64_t> v;
+  for (int64_t a = 1; a <= hi; a *= 2)
+    for (int64_t b = a; b <= hi; b *= 3)
+      for (int64_t c = b; c <= hi; c *= 5)
+        if (c >= lo) v.push_back(c);
+  std::sort(v.begin(), v.end());
+  return v;
+}
+
+bool is_smooth(int64_t x) {
+  if (x < 1) return false;
+  for (int f : {2, 3, 5})
+    while (x % f == 0) x /= f;
+  return x == 1;
+}
+
+// radix plan of a 5-smooth length: radix 8 and 4 first, then 2, 5, 3.
+int radix_plan(int L, int* rad) {
+  int n = 0;
+  while (L % 8 == 0 && L > 8) {
+    rad[n++] = 8;
+    L /= 8;
+  }
+  while (L % 4 == 0) {
+    rad[n++] = 4;
+    L /= 4;
+  }
+  while (L % 8 == 0) {
+    rad[n++] = 8;
+    L /= 8;
+  }
+  while (L % 2 == 0) {
+    rad[n++] = 2;
+    L /= 2;
+  }
+  while (L % 5 == 0) {
+    rad[n++] = 5;
+    L /= 5;
+  }
+  while (L % 3 == 0) {
+    rad[n++] = 3;
+    L /= 3;
+  }
+  return n;
+}
+
+int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+// Split m into k factors, each a 5-smooth length in [2, lmax]; prefers
+// balanced factors (largest minimal columns per workgroup).  Returns false
+// when impossible.
+bool split_mid(int64_t m, int k, int lmax, std::vector<int>* out) {
+  if (k == 0) return m == 1;
+  if (k == 1) {
+    if (m >= 2 && m <= lmax && is_smooth(m)) {
+      out->push_back((int)m);
+      return true;
+    }
+    return false;
+  }
+  if (m < ((int64_t)1 << k)) return false;
+  {
+    double cap = std::pow((double)lmax, (double)k);
+    if ((double)m > cap * (1.0 + 1e-12)) return false;
+  }
+  // target ~ m^(1/k); try divisors closest to it first
+  double target = std::pow((double)m, 1.0 / k);
+  std::vector<int> cands;
+  for (int L = 2; L <= lmax; ++L)
+    if (m % L == 0 && is_smooth(L)) cands.push_back(L);
+  std::sort(cands.begin(), cands.end(), [&](int a, int b) {
+    return std::fabs(std::log(a / target)) < std::fabs(std::log(b / target));
+  });
+  for (int L : cands) {
+    std::vector<int> rest;
+    if (split_mid(m / L, k - 1, lmax, &rest)) {
+      out->push_back(L);
+      out->insert(out->end(), rest.begin(), rest.end());
+      return true;
+    }
+  }
+  return false;
+}
+
+}  // namespace
+
+double default_sigma(int prec) { return prec == 1 ? 1.5 : 1.25; }
+
+// Upsampling factor for a tolerance: the precision's default, or 2 when the
+// default would need a kernel wider than kMaxWidth cells.
+static double choose_sigma(double eps, int prec) {
+  const double s = default_sigma(prec);
+  const double w = std::log(2.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / s));
+  return w > kMaxWidth ? 2.0 : s;
+}
+
+// The estimate exp(-pi w sqrt(1 - 1/sigma)) runs ~1.6x below the measured
+// worst-case error of the sums, so the width is sized for eps / 2.
+int kernel_width(double eps, double sigma) {
+  double w = std::ceil(std::log(2.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma)));
+  int wi = (int)w;
+  return std::min(kMaxWidth, std::max(2, wi));
+}
+
+double kernel_beta(int w, double sigma) { return 0.97 * M_PI * w * (1.0 - 1.0 / (2.0 * sigma)); }
+
+bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
+  Plan p{};
+  p.prec = r.prec;
+  p.nf = r.nf;
+  p.K = r.nf / 2;
+  const double smin = r.sigma > 1.0 ? r.sigma : choose_sigma(r.eps, r.prec);
+  const int wguess = kernel_width(r.eps, smin);
+  int64_t nmin = (int64_t)std::ceil(smin * (double)r.nf);
+  nmin = std::max<int64_t>(nmin, 2 * wguess + 2);
+  nmin = std::max<int64_t>(nmin, 16);
+  const int G = r.G;
+  const int emid = r.prec == 1 ? kEmid32 : kEmid64;
+  const int elast = r.prec == 1 ? kElast32 : kElast64;
+  const int cmax = r.prec == 1 ? 32 : 16;
+
+  auto cand = smooth_in_range(nmin, 2 * nmin + 64);
+  double best_cost = 1e300;
+  int best_np = 0;
+  int64_t best_n = 0;
+  std::vector<int> best_len;
+  for (int np = 1; np <= kMaxPass; ++np) {
+    for (int64_t n : cand) {
+      double cost = (double)n * (np == 1 ? 1.0 : 2.0 * np - 1.0);
+      if (cost >= best_cost) break;
+      std::vector<int> lens;
+      bool ok = false;
+      if (np == 1) {
+        if (G * (n + 1) <= elast && n <= kLmaxPass) {
+          lens.push_back((int)n);
+          ok = true;
+        }
+      } else {
+        // last length: largest with >= 4 rows per workgroup
+        const int llast_max = std::min<int64_t>(elast / (G * 4) - 1, kLmaxPass);
+        for (int Ll = llast_max; Ll >= 2 && !ok; --Ll) {
+          if (n % Ll || !is_smooth(Ll)) continue;
+          std::vector<int> mids;
+          if (split_mid(n / Ll, np - 1, std::min(kLmaxPass, emid / 4), &mids)) {
+            lens = mids;
+            lens.push_back(Ll);
+            ok = true;
+          }
+        }
+      }
+      if (ok) {
+        best_cost = cost;
+        best_np = np;
+        best_n = n;
+        best_len = lens;
+        break;
+      }
+    }
+  }
+  if (!best_np) {
+    if (err) *err = "no supported FFT factorisation for this number of frequencies";
+    return false;
+  }
+  p.n = best_n;
+  p.sigma = (double)best_n / (double)r.nf;
+  p.w = kernel_width(r.eps, p.sigma);
+  // a grid that fits one workgroup costs nothing extra with the widest kernel,
+  // and tiny problems (a handful of frequencies, huge sigma) need the margin:
+  // the floating-mean cancellation at the lowest frequencies amplifies the
+  // error of the sums there
+  if (best_np == 1) p.w = std::max(p.w, std::min<int>(kMaxWidth, (int)(best_n / 2) - 1));
+  p.beta = kernel_beta(p.w, p.sigma);
+  p.hw = 0.5 * p.w;
+  p.npass = best_np;
+  int64_t before = 1;
+  for (int i = 0; i < best_np; ++i) {
+    FftPass& ps = p.pass[i];
+    ps.L = best_len[i];
+    ps.P = before;
+    ps.S = best_n / (before * ps.L);
+    before *= ps.L;
+    ps.nrad = radix_plan(ps.L, ps.rad);
+    if (i + 1 < best_np) {
+      int c = std::min(cmax, pow2_floor(emid / ps.L));
+      if (ps.S < c) c = (int)std::max<int64_t>(1, ps.S);
+      ps.C = c;
+    } else {
+      int d = 1;
+      while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P) d *= 2;
+      ps.C = d;
+      p.D = d;
+    }
+  }
+  if (best_np == 1) {
+    p.S1 = best_n;
+    p.nrows = 1;
+  } else {
+    p.nrows = p.pass[0].L;
+    p.S1 = best_n / p.nrows;
+  }
+  int T = 1;
+  for (int d = (int)std::min<int64_t>(p.S1, kTileMaxCells); d >= 1; --d)
+    if (p.S1 % d == 0) {
+      T = d;
+      break;
+    }
+  p.T = T;
+  p.Tb = best_n >= 4096 ? 32 : 8;
+  p.nbins = (best_n + p.Tb - 1) / p.Tb;
+  if (out) *out = p;
+  return true;
+}
+
+void make_twiddles(Plan* p, std::vector<double>* tw) {
+  tw->clear();
+  auto push_root = [&](int64_t x, int64_t N) {
+    long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)x / (long double)N;
+    tw->push_back((double)cosl(ang));
+    tw->push_back((double)sinl(ang));
+  };
+  for (int i = 0; i < p->npass; ++i) {
+    FftPass& ps = p->pass[i];
+    ps.twL_off = (int64_t)(tw->size() / 2);
+    for (int x = 0; x < ps.L; ++x) push_root(x, ps.L);
+    if (i + 1 < p->npass) {
+      const int64_t N = (int64_t)ps.L * ps.S;
+      int b = 0;
+      while (((int64_t)1 << (2 * b)) < N) ++b;
+      ps.bshift = b;
+      const int64_t B = (int64_t)1 << b;
+      ps.twlo_off = (int64_t)(tw->size() / 2);
+      for (int64_t x = 0; x < B; ++x) push_root(x, N);
+      ps.twhi_off = (int64_t)(tw->size() / 2);
+      const int64_t nh = (N + B - 1) / B;
+      for (int64_t x = 0; x < nh; ++x) push_root(x * B % N, N);
+    } else {
+      ps.bshift = 0;
+      ps.twlo_off = ps.twhi_off = 0;
+    }
+  }
+  p->tw_count = (int64_t)(tw->size() / 2);
+}
+
+void phihat_nodes(const Plan& p, std::vector<double>* z, std::vector<double>* gphi) {
+  int q = 2 * p.w + 16;
+  if (q % 2) ++q;
+  z->clear();
+  gphi->clear();
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int i = 1; i <= q / 2; ++i) {
+    long double x = cosl(pi * (i - 0.25L) / (q + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= q; ++k) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (x * p1 - p0) / (x * x - 1.0L);
+      long double dx = p1 / dp;
+      x -= dx;
+      if (fabsl(dx) < 1e-19L) break;
+    }
+    {
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= q; ++k) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (x * p1 - p0) / (x * x - 1.0L);
+    }
+    long double g = 2.0L / ((1.0L - x * x) * dp * dp);
+    long double phi = expl((long double)p.beta * (sqrtl(1.0L - x * x) - 1.0L));
+    z->push_back((double)x);
+    gphi->push_back((double)(g * phi));
+  }
+}
+
+size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~(size_t)255;
+    char* ptr = base ? base + off : nullptr;
+    off += bytes;
+    return ptr;
+  };
+  Work x{};
+  x.stats = reinterpret_cast<DevStats*>(take(sizeof(DevStats)));
+  x.partials = reinterpret_cast<double*>(take(sizeof(double) * 8 * kStatsBlocks));
+  x.bin_start = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
+  x.bin_count = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
+  x.bin_cursor = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
+  const int64_t nchunks = (p.nbins + 1 + 2047) / 2048;
+  x.scan_part = reinterpret_cast<int*>(take(sizeof(int) * (nchunks + 1)));
+  x.ts = reinterpret_cast<double*>(take(sizeof(double) * nd));
+  if (G == 3) {
+    x.ys = reinterpret_cast<double*>(take(sizeof(double) * nd));
+    x.dys = reinterpret_cast<double*>(take(sizeof(double) * nd));
+  } else {
+    x.hs = reinterpret_cast<double*>(take(sizeof(double) * nd));
+  }
+  x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
+  x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));
+  const size_t cbytes = p.prec == 1 ? 8 : 16;
+  for (int g = 0; g < G; ++g) x.grid[g] = take(cbytes * p.n);
+  if (p.npass >= 3)
+    for (int g = 0; g < G; ++g) x.grid2[g] = take(cbytes * p.n);
+  off = (off + 255) & ~(size_t)255;
+  if (w) *w = x;
+  return off;
+}
+
+}  // namespace mils

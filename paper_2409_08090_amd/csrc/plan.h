@@ -1,0 +1,48 @@
+// plan.h -- host-side planner: kernel width and shape from the tolerance,
+// fine-grid size and its multi-pass FFT factorisation, twiddle tables and the
+// quadrature nodes of the kernel's Fourier transform.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "mils_internal.h"
+
+namespace mils {
+
+struct PlanRequest {
+  int64_t nf;
+  double eps;
+  int prec;             // 0 FP64, 1 FP32
+  int G;                // grids transformed together in the last pass (3 or 1)
+  double sigma = 0.0;   // upsampling factor; 0 = the precision's default
+};
+
+// Default upsampling factor of a precision.
+double default_sigma(int prec);
+
+// Kernel width for tolerance eps at upsampling sigma (clamped to [2, 16]).
+int kernel_width(double eps, double sigma);
+
+// Shape parameter of the exponential-of-semicircle kernel.
+double kernel_beta(int w, double sigma);
+
+// Build the plan; returns false (with a message) when no supported
+// factorisation exists.
+bool make_plan(const PlanRequest& r, Plan* out, std::string* err);
+
+// Twiddle tables of the plan, as interleaved (re, im) pairs in FP64; the
+// caller narrows them to FP32 for FP32 plans.  Offsets are stored in the plan.
+void make_twiddles(Plan* p, std::vector<double>* tw);
+
+// Gauss-Legendre nodes z_r in (0, 1) and the products g_r * phi(z_r) used by
+// the phihat kernel (even rule of q points on [-1, 1], positive half).
+void phihat_nodes(const Plan& p, std::vector<double>* z, std::vector<double>* gphi);
+
+// Device workspace layout of one call; returns the byte size.  With base ==
+// nullptr only the size is computed.
+size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w);
+
+}  // namespace mils

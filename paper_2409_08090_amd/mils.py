@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libmils (include/mils.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libmils.so.  torch is used for device memory and streams; arrays
+are passed to the library as raw device pointers.  There is no CPU fallback:
+if libmils.so is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmils.so")
+
+MILS_OK = 0
+MILS_ERR_INVALID_ARG = -1
+MILS_ERR_DEGENERATE = -2
+MILS_ERR_OOM = -3
+MILS_ERR_DEVICE = -4
+MILS_ERR_UNSUPPORTED = -5
+MILS_ERR_BUSY = -6
+MILS_ERR_CANCELLED = -7
+MILS_ERR_TIMEOUT = -8
+
+PRECISIONS = {"fp64": 0, "fp32": 1}
+NORMALIZATIONS = {"standard": 0, "model": 1, "log": 2, "psd": 3}
+MILS_CENTER_DATA = 1
+MILS_FIT_MEAN = 2
+
+
+class mils_params(ctypes.Structure):
+    _fields_ = [("f0", ctypes.c_double), ("df", ctypes.c_double), ("nf", ctypes.c_int64),
+                ("eps", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("normalization", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class mils_plan_desc(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("width", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("n", ctypes.c_int64), ("npass", ctypes.c_int32), ("len", ctypes.c_int32 * 4),
+                ("tile", ctypes.c_int32), ("bin", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+class MilsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libmils error {status}: {message}")
+        self.status = status
+
+
+_lib = None
+_lock = threading.Lock()
+
+# Exported symbols and their ctypes signatures (mirrors include/mils.h).
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I64P = ctypes.POINTER(ctypes.c_int64)
+SIGNATURES = {
+    "mils_version": ([], ctypes.c_int),
+    "mils_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "mils_last_error": ([_P], ctypes.c_char_p),
+    "mils_context_create": ([ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)], ctypes.c_int),
+    "mils_context_destroy": ([_P], ctypes.c_int),
+    "mils_plan_info": ([_P, ctypes.c_int64, ctypes.POINTER(mils_params),
+                        ctypes.POINTER(mils_plan_desc)], ctypes.c_int),
+    "mils_check_periodogram_args": ([_P, _P, ctypes.c_int64, ctypes.POINTER(mils_params), _P],
+                                    ctypes.c_int),
+    "mils_trig_sums": ([_P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                        ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P], ctypes.c_int),
+    "mils_periodogram": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params), _P, _P],
+                         ctypes.c_int),
+    "mils_periodogram_async": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params),
+                                _P, _P], ctypes.c_int),
+    "mils_context_status": ([_P], ctypes.c_int),
+    "mils_periodogram_batch": ([_P, ctypes.c_int64, _I64P, _P, _P, _P, _I64P, _D, _D,
+                                ctypes.POINTER(mils_params), _P,
+                                ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
+    "mils_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
+    "mils_profile_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+    "mils_profile_read": ([_P, _D, _I64P], ctypes.c_int),
+}
+
+MILS_NUM_STAGES = 8
+
+
+def load():
+    """Load libmils.so (raises when it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2409_08090_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def status_str(code: int) -> str:
+    return load().mils_status_str(code).decode()
+
+
+def version() -> int:
+    return int(load().mils_version())
+
+
+class Context:
+    """A libmils context on one device (device=-1: host-only planning context)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        lib = load()
+        h = _P()
+        rc = lib.mils_context_create(int(device), int(hbm_budget_bytes), ctypes.byref(h))
+        if rc != MILS_OK:
+            raise MilsError(rc, lib.mils_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().mils_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return load().mils_last_error(self.handle).decode()
+
+    def profile_enable(self, enable: bool = True):
+        self.check(load().mils_profile_enable(self.handle, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """{stage name: (total ms, launches)} since the last read / enable."""
+        import numpy as np
+        ms = np.zeros(MILS_NUM_STAGES)
+        n = np.zeros(MILS_NUM_STAGES, dtype=np.int64)
+        self.check(load().mils_profile_read(self.handle, ms.ctypes.data_as(_D),
+                                            n.ctypes.data_as(_I64P)))
+        lib = load()
+        return {lib.mils_profile_stage_name(i).decode(): (float(ms[i]), int(n[i]))
+                for i in range(MILS_NUM_STAGES) if n[i]}
+
+    def check(self, rc: int):
+        if rc != MILS_OK:
+            raise MilsError(rc, self.last_error())
+        return rc
+
+
+_contexts: dict[int, Context] = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    with _lock:
+        ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        with _lock:
+            _contexts[device] = ctx
+    return ctx
+
+
+def make_params(f0, df, nf, eps=1e-9, precision="fp64", normalization="standard",
+                center_data=True, fit_mean=True) -> mils_params:
+    flags = (MILS_CENTER_DATA if center_data else 0) | (MILS_FIT_MEAN if fit_mean else 0)
+    return mils_params(float(f0), float(df), int(nf), float(eps), PRECISIONS[precision],
+                       NORMALIZATIONS[normalization], flags)
+
+
+def plan_info(nd, nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01) -> dict:
+    """Planner decision for a periodogram (host only, no GPU needed)."""
+    lib = load()
+    ctx = Context(-1)
+    p = make_params(f0, df, nf, eps, precision)
+    d = mils_plan_desc()
+    ctx.check(lib.mils_plan_info(ctx.handle, int(nd), ctypes.byref(p), ctypes.byref(d)))
+    out = {"sigma": d.sigma, "width": d.width, "beta": d.beta, "n": d.n, "npass": d.npass,
+           "len": list(d.len)[:d.npass], "tile": d.tile, "bin": d.bin,
+           "workspace_bytes": d.workspace_bytes}
+    ctx.close()
+    return out
+
+
+def _dev_f64(x, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA/HIP torch tensor")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return x
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization="standard",
+                center_data=True, fit_mean=True, out=None, stream=None, ctx=None, sync=True):
+    """Lomb-Scargle power at f0 + k df, k < nf (float64 device tensor)."""
+    import torch
+    t = _dev_f64(t, "t")
+    y = _dev_f64(y, "y")
+    if dy is not None:
+        dy = _dev_f64(dy, "dy")
+    if out is None:
+        out = torch.empty(int(nf), dtype=torch.float64, device=t.device)
+    ctx = ctx or default_context(t.device.index)
+    p = make_params(f0, df, nf, eps, precision, normalization, center_data, fit_mean)
+    fn = load().mils_periodogram if sync else load().mils_periodogram_async
+    rc = fn(ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+            ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, int(t.numel()),
+            ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    ctx.check(rc)
+    return out
+
+
+def context_status(ctx=None) -> int:
+    ctx = ctx or default_context()
+    return load().mils_context_status(ctx.handle)
+
+
+def trig_sums(t, h, f0, df, nf, eps=1e-9, precision="fp64", stream=None, ctx=None):
+    """sum_j h_j exp(+2 pi i (f0 + k df) t_j), k < nf (complex128 device tensor)."""
+    import torch
+    t = _dev_f64(t, "t")
+    h = _dev_f64(h, "h")
+    out = torch.empty(2 * int(nf), dtype=torch.float64, device=t.device)
+    ctx = ctx or default_context(t.device.index)
+    rc = load().mils_trig_sums(ctx.handle, ctypes.c_void_p(t.data_ptr()),
+                               ctypes.c_void_p(h.data_ptr()), int(t.numel()), float(f0),
+                               float(df), int(nf), float(eps), PRECISIONS[precision],
+                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    ctx.check(rc)
+    return torch.view_as_complex(out.view(-1, 2))
+
+
+def periodogram_batch(t, y, dy, nd_off, nf_off, f0, df, eps=1e-9, precision="fp64",
+                      normalization="standard", center_data=True, fit_mean=True, out=None,
+                      stream=None, ctx=None, return_status=False):
+    """Batched periodograms in CSR layout.  t, y, dy: concatenated device
+    tensors; nd_off, nf_off: int64 offsets (ncurves + 1, host numpy);
+    f0, df: per-curve float64 (host numpy)."""
+    import numpy as np
+    import torch
+    t = _dev_f64(t, "t")
+    y = _dev_f64(y, "y")
+    if dy is not None:
+        dy = _dev_f64(dy, "dy")
+    nd_off = np.ascontiguousarray(nd_off, dtype=np.int64)
+    nf_off = np.ascontiguousarray(nf_off, dtype=np.int64)
+    f0 = np.ascontiguousarray(f0, dtype=np.float64)
+    df = np.ascontiguousarray(df, dtype=np.float64)
+    nc = nd_off.size - 1
+    if out is None:
+        out = torch.empty(int(nf_off[-1]), dtype=torch.float64, device=t.device)
+    st = np.zeros(nc, dtype=np.int32)
+    ctx = ctx or default_context(t.device.index)
+    p = make_params(0.0, 1.0, 1, eps, precision, normalization, center_data, fit_mean)
+    rc = load().mils_periodogram_batch(
+        ctx.handle, nc, nd_off.ctypes.data_as(_I64P), ctypes.c_void_p(t.data_ptr()),
+        ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(dy.data_ptr()) if dy is not None else None,
+        nf_off.ctypes.data_as(_I64P), f0.ctypes.data_as(_D), df.ctypes.data_as(_D),
+        ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream_ptr(stream))
+    if rc not in (MILS_OK, MILS_ERR_INVALID_ARG, MILS_ERR_DEGENERATE) or not return_status:
+        ctx.check(rc)
+    return (out, st) if return_status else out

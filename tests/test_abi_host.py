@@ -1,0 +1,141 @@
+"""Host-side tests of the C ABI (no GPU): the library loads and exports every
+symbol of include/mils.h, argument validation returns the documented codes,
+and the planner's choices satisfy their invariants."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2409_08090_amd import mils
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^[A-Za-z_][\w \*]*?\b(mils_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = mils.load()
+    names = header_functions()
+    assert "mils_periodogram" in names and "mils_trig_sums" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+    # and the binding knows each of them
+    assert set(names) <= set(mils.SIGNATURES), set(names) - set(mils.SIGNATURES)
+
+
+def test_version_and_status_strings():
+    assert mils.version() == 10000
+    assert mils.status_str(0) == "ok"
+    assert "invalid" in mils.status_str(-1)
+
+
+@pytest.fixture
+def host_ctx():
+    c = mils.Context(-1)
+    yield c
+    c.close()
+
+
+def _check(t, y, nd, p, power):
+    return mils.load().mils_check_periodogram_args(t, y, nd, ctypes.byref(p) if p else None, power)
+
+
+def test_argument_validation_codes():
+    ok = mils.make_params(0.01, 0.01, 100)
+    P = ctypes.c_void_p(16)  # any non-null pointer: nothing is dereferenced
+    assert _check(P, P, 10, ok, P) == mils.MILS_OK
+    assert _check(None, P, 10, ok, P) == mils.MILS_ERR_INVALID_ARG
+    assert _check(P, None, 10, ok, P) == mils.MILS_ERR_INVALID_ARG
+    assert _check(P, P, 10, ok, None) == mils.MILS_ERR_INVALID_ARG
+    assert _check(P, P, 0, ok, P) == mils.MILS_ERR_INVALID_ARG
+    assert _check(P, P, 2 ** 31, ok, P) == mils.MILS_ERR_INVALID_ARG
+    assert _check(P, P, 10, None, P) == mils.MILS_ERR_INVALID_ARG
+    bad = [
+        mils.make_params(0.01, 0.0, 100),
+        mils.make_params(0.01, -1.0, 100),
+        mils.make_params(float("nan"), 0.01, 100),
+        mils.make_params(0.01, float("inf"), 100),
+        mils.make_params(0.01, 0.01, 0),
+    ]
+    for p in bad:
+        assert _check(P, P, 10, p, P) == mils.MILS_ERR_INVALID_ARG
+    p = mils.make_params(0.01, 0.01, 100)
+    p.precision = 7
+    assert _check(P, P, 10, p, P) == mils.MILS_ERR_INVALID_ARG
+    p = mils.make_params(0.01, 0.01, 100)
+    p.normalization = 9
+    assert _check(P, P, 10, p, P) == mils.MILS_ERR_INVALID_ARG
+    p = mils.make_params(0.01, 0.01, 100)
+    p.flags = 8
+    assert _check(P, P, 10, p, P) == mils.MILS_ERR_INVALID_ARG
+    # tolerance outside the precision's range, or too many frequencies
+    assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, eps=1e-15), P) == mils.MILS_ERR_UNSUPPORTED
+    assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, eps=1e-7, precision="fp32"),
+                  P) == mils.MILS_ERR_UNSUPPORTED
+    assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, eps=0.5), P) == mils.MILS_ERR_UNSUPPORTED
+    assert _check(P, P, 10, mils.make_params(0.01, 0.01, 2 ** 28 + 1), P) == mils.MILS_ERR_UNSUPPORTED
+
+
+def test_host_only_context_refuses_compute(host_ctx):
+    lib = mils.load()
+    p = mils.make_params(0.01, 0.01, 100)
+    P = ctypes.c_void_p(16)
+    rc = lib.mils_periodogram(host_ctx.handle, P, P, None, 10, ctypes.byref(p), P, None)
+    assert rc == mils.MILS_ERR_DEVICE
+    rc = lib.mils_trig_sums(host_ctx.handle, P, P, 10, 0.0, 0.1, 10, 1e-9, 0, P, None)
+    assert rc == mils.MILS_ERR_DEVICE
+    # invalid arguments are rejected before the device is considered
+    rc = lib.mils_periodogram(host_ctx.handle, None, P, None, 10, ctypes.byref(p), P, None)
+    assert rc == mils.MILS_ERR_INVALID_ARG
+    assert lib.mils_periodogram(None, P, P, None, 10, ctypes.byref(p), P, None) == \
+        mils.MILS_ERR_INVALID_ARG
+
+
+def _smooth(n):
+    for f in (2, 3, 5):
+        while n % f == 0:
+            n //= f
+    return n == 1
+
+
+@pytest.mark.parametrize("nf,eps,prec", [
+    (12_000, 1e-9, "fp64"), (12_000_000, 1e-9, "fp64"), (12_000_000, 1e-5, "fp32"),
+    (1, 1e-9, "fp64"), (7, 1e-9, "fp64"), (1200, 1e-5, "fp32"), (120_000, 1e-9, "fp64"),
+    (2 ** 28, 1e-9, "fp64"), (999_983, 1e-6, "fp32"), (240_000, 1e-12, "fp64"),
+])
+def test_planner_invariants(nf, eps, prec):
+    d = mils.plan_info(nd=1000, nf=nf, eps=eps, precision=prec)
+    n = d["n"]
+    assert n >= math.ceil((1.25 if prec == "fp64" else 1.5) * nf) - 1
+    assert _smooth(n)
+    assert math.prod(d["len"]) == n
+    assert 1 <= d["npass"] <= 4
+    assert 2 <= d["width"] <= 16
+    # the ES aliasing estimate exp(-pi w sqrt(1 - 1/sigma)) meets the tolerance
+    assert math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])) <= eps / 2 * 1.0001
+    assert n % d["tile"] == 0 and d["tile"] <= 1024
+
+
+def test_kernel_error_estimate_falls_with_tolerance():
+    est = []
+    for eps in (1e-3, 1e-6, 1e-9, 1e-12, 1e-14):
+        d = mils.plan_info(1000, 100_000, eps)
+        est.append(math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])))
+    assert est == sorted(est, reverse=True) and est[0] > 100 * est[-1]
+    # at fixed sigma the width grows as the tolerance shrinks
+    ws = [mils.plan_info(1000, 100_000, eps)["width"] for eps in (1e-3, 1e-6, 1e-9)]
+    assert ws == sorted(ws) and ws[0] < ws[-1]
+
+
+def test_cfg1_shape_uses_three_lds_passes():
+    d = mils.plan_info(nd=1_000_000, nf=12_000_000, eps=1e-9)
+    assert d["npass"] == 3 and d["n"] >= 15_000_000 and d["width"] == 16

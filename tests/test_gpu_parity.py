@@ -1,0 +1,214 @@
+"""GPU parity of the HIP path against the CPU oracle.
+
+Every case draws seeded synthetic inputs (paper_2409_08090_amd.workloads),
+runs the periodogram or the raw trigonometric sums through the C ABI, and
+compares with the oracle element by element:
+  FP64 at eps=1e-9: max|P - P_ref| / max|P_ref| <= 1e-8
+  FP32 at eps=1e-5: max|P - P_ref| / max|P_ref| <= 1e-4
+  raw sums:         max|g - g_ref| <= 10 eps sum_j |h_j|
+(the tolerances of the NUFFT Lomb-Scargle path; sums are judged in the norm
+in which the NUFFT tolerance is defined).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle  # noqa: E402
+from paper_2409_08090_amd import mils, workloads  # noqa: E402
+
+TOL = {"fp64": 1e-8, "fp32": 1e-4}
+EPS = {"fp64": 1e-9, "fp32": 1e-5}
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def gpu_power(c, precision="fp64", dy=True, **kw):
+    p = mils.periodogram(dev(c.t), dev(c.y), dev(c.dy) if dy else None, c.f0, c.df, c.nf,
+                         eps=kw.pop("eps", EPS[precision]), precision=precision, **kw)
+    torch.cuda.synchronize()
+    return p.cpu().numpy()
+
+
+def rel_err(p, ref, mask=None):
+    if mask is not None:
+        p, ref = p[mask], ref[mask]
+    return np.max(np.abs(p - ref)) / np.max(np.abs(ref))
+
+
+def report(name, p, ref):
+    """Median and 99th percentile of the per-frequency relative error, the
+    error distribution the paper reports (Sec. 2.2), printed for the log."""
+    r = np.abs(p - ref) / np.maximum(np.abs(ref), 1e-300)
+    print(f"[{name}] max-normalised {rel_err(p, ref):.3e}  median {np.median(r):.3e}  "
+          f"p99 {np.percentile(r, 99):.3e}", flush=True)
+
+
+# ---------------------------------------------------------------- small single curve
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_small_full_grid(precision):
+    c = workloads.single_small(seed=0)
+    p = gpu_power(c, precision)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf)
+    report(f"single_small {precision}", p, ref)
+    assert rel_err(p, ref) <= TOL[precision]
+
+
+def test_noiseless_sinusoid_power_is_one():
+    c = workloads.single_small(seed=0, noiseless=True)
+    p = gpu_power(c)
+    assert abs(p[184] - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("normalization", ["standard", "model", "log", "psd"])
+@pytest.mark.parametrize("center_data,fit_mean", [(True, True), (False, True), (True, False),
+                                                  (False, False)])
+def test_normalizations_and_flags(normalization, center_data, fit_mean):
+    c = workloads.uniform_series(seed=21, nd=700, nf=5000, span=50.0)
+    c.y = c.y + 2.5  # a non-zero mean exercises the centring / floating-mean terms
+    p = gpu_power(c, normalization=normalization, center_data=center_data, fit_mean=fit_mean)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf, normalization=normalization,
+                             center_data=center_data, fit_mean=fit_mean)
+    assert rel_err(p, ref) <= 1e-8
+
+
+def test_unit_weights_and_unsorted_times():
+    c = workloads.uniform_series(seed=5, nd=900, nf=7000, span=30.0, sorted_t=False)
+    p = gpu_power(c, dy=False)
+    ref = oracle.periodogram(c.t, c.y, None, c.f0, c.df, nf=c.nf)
+    assert rel_err(p, ref) <= 1e-8
+    # the same points in sorted order give the same power
+    o = np.argsort(c.t)
+    c2 = workloads.Curve(c.t[o], c.y[o], c.dy[o], c.f0, c.df, c.nf)
+    p2 = gpu_power(c2, dy=False)
+    assert np.max(np.abs(p2 - p)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_times_spanning_more_than_one_grid_period():
+    """df * span > 1: the grid coordinates wrap, forcing the counting sort."""
+    c = workloads.uniform_series(seed=9, nd=500, nf=3000, span=100.0)
+    c.df = 0.031  # df * span = 3.1
+    c.f0 = 0.013
+    p = gpu_power(c)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf)
+    assert rel_err(p, ref) <= 1e-8
+
+
+def test_exact_fit_degenerate_case():
+    """Three points and a floating mean: the three-parameter model fits exactly,
+    so P = 1 at every frequency.  The fit's determinant D is tiny here, which
+    amplifies the NUFFT error of the sums by ~1/D; the bound is looser."""
+    c = workloads.uniform_series(seed=8, nd=3, nf=5, span=20.0)
+    p = gpu_power(c)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf)
+    np.testing.assert_allclose(ref, 1.0, atol=1e-12)
+    assert np.max(np.abs(p - 1.0)) <= 1e-4
+
+
+@pytest.mark.parametrize("nd,nf", [(40, 1), (64, 100), (1000, 1201), (257, 2000),
+                                   (5000, 60000), (20000, 240000)])
+def test_sizes_and_ragged_tails(nd, nf):
+    c = workloads.uniform_series(seed=nd + nf, nd=nd, nf=nf, span=20.0)
+    p = gpu_power(c)
+    k = np.arange(nf) if nf <= 20000 else np.unique(np.concatenate(
+        [np.arange(500), np.arange(nf - 500, nf),
+         np.random.default_rng(1).integers(0, nf, 2000)]))
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+    assert rel_err(p[k], ref) <= 1e-8
+
+
+def test_zero_frequency_and_negative_frequencies():
+    c = workloads.uniform_series(seed=2, nd=300, nf=401, span=10.0)
+    c.f0 = -200 * c.df  # f_200 == 0 exactly
+    p = gpu_power(c)
+    ref, fl = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf, return_flags=True)
+    assert p[200] == 0.0 and fl[200] == 1
+    ok = fl == 0
+    assert rel_err(p, ref, ok) <= 1e-8
+    # the power is even in f
+    np.testing.assert_allclose(p, p[::-1], rtol=0, atol=1e-9 * np.max(p))
+
+
+# ---------------------------------------------------------------- raw trig sums
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trig_sums_match_direct_sums(precision):
+    rng = np.random.default_rng(3)
+    nd, nf = 2000, 20000
+    t = np.sort(rng.uniform(-50, 250, nd))
+    h = rng.normal(size=nd)
+    f0, df = -3.7, 0.00071
+    eps = EPS[precision]
+    g = mils.trig_sums(dev(t), dev(h), f0, df, nf, eps=eps, precision=precision)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    ref = oracle.trig_sums(t, h, f0, df, nf=nf)
+    err = np.max(np.abs(g - ref)) / np.sum(np.abs(h))
+    print(f"[trig_sums {precision}] max error / sum|h| = {err:.3e}", flush=True)
+    assert err <= 10 * eps
+
+
+def test_trig_sums_error_falls_with_tolerance():
+    rng = np.random.default_rng(4)
+    nd, nf = 800, 6000
+    t = rng.uniform(0, 40, nd)
+    h = rng.normal(size=nd)
+    ref = oracle.trig_sums(t, h, 0.0, 0.005, nf=nf)
+    errs = []
+    for eps in (1e-3, 1e-6, 1e-9, 1e-12):
+        g = mils.trig_sums(dev(t), dev(h), 0.0, 0.005, nf, eps=eps).cpu().numpy()
+        errs.append(np.max(np.abs(g - ref)) / np.sum(np.abs(h)))
+    print("[trig_sums] error vs eps:", ["%.2e" % e for e in errs], flush=True)
+    for e, eps in zip(errs, (1e-3, 1e-6, 1e-9, 1e-12)):
+        assert e <= 10 * eps
+    assert errs[0] > errs[1] > errs[2]
+
+
+# ---------------------------------------------------------------- device-side checks
+def test_invalid_values_and_constant_data():
+    c = workloads.uniform_series(seed=1, nd=100, nf=500, span=10.0)
+    y = c.y.copy()
+    y[17] = np.nan
+    with pytest.raises(mils.MilsError) as e:
+        mils.periodogram(dev(c.t), dev(y), dev(c.dy), c.f0, c.df, c.nf)
+    assert e.value.status == mils.MILS_ERR_INVALID_ARG
+    dy = c.dy.copy()
+    dy[3] = 0.0
+    with pytest.raises(mils.MilsError) as e:
+        mils.periodogram(dev(c.t), dev(c.y), dev(dy), c.f0, c.df, c.nf)
+    assert e.value.status == mils.MILS_ERR_INVALID_ARG
+    with pytest.raises(mils.MilsError) as e:
+        mils.periodogram(dev(c.t), dev(np.full(100, 3.0)), dev(c.dy), c.f0, c.df, c.nf)
+    assert e.value.status == mils.MILS_ERR_DEGENERATE
+    # the context keeps working after content errors
+    p = gpu_power(c)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf)
+    assert rel_err(p, ref) <= 1e-8
+
+
+# ---------------------------------------------------------------- full-size single curve
+def _large_sample(c, peaks=True):
+    rng = np.random.default_rng(2)
+    nf = c.nf
+    parts = [rng.integers(0, nf, 150), np.arange(60), np.arange(nf - 60, nf)]
+    return np.unique(np.concatenate(parts))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_single_large_full_size_sampled(precision):
+    c = workloads.single_large(seed=1)
+    p = gpu_power(c, precision)
+    k = _large_sample(c)
+    # the periodogram's peaks: strongest GPU frequencies (checked one by one)
+    top = np.argsort(p)[-40:]
+    k = np.unique(np.concatenate([k, top]))
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+    err = np.max(np.abs(p[k] - ref)) / np.max(np.abs(ref))
+    print(f"[single_large {precision}] max-normalised error on {k.size} sampled frequencies: "
+          f"{err:.3e}", flush=True)
+    assert err <= TOL[precision]
+    assert np.all(np.isfinite(p)) and p.min() >= -1e-6 and p.max() <= 1 + 1e-6
