@@ -50,6 +50,34 @@ __device__ __forceinline__ void grid_coord(double t, double tau, double g, doubl
   frac = d;
 }
 
+// The same with 32-bit cell indices (grids up to 2^31 cells).
+__device__ __forceinline__ void grid_coord32(double t, double tau, double g, double nd_, int n,
+                                             int& cell, double& frac) {
+  double th, tl;
+  dd_two_sum(t, -tau, th, tl);
+  double ph, pl;
+  dd_two_prod(g, th, ph, pl);
+  pl = __builtin_fma(g, tl, pl);
+  double fh = ph - floor(ph);  // exact
+  double uh, ul;
+  dd_two_prod(nd_, fh, uh, ul);
+  ul = __builtin_fma(nd_, pl, ul);
+  double ci = floor(uh);
+  double d = (uh - ci) + ul;
+  double fl = floor(d);
+  ci += fl;
+  d -= fl;
+  if (d >= 1.0) {
+    d -= 1.0;
+    ci += 1.0;
+  }
+  int c = (int)ci;
+  if (c >= n) c -= n;
+  if (c < 0) c += n;
+  cell = c;
+  frac = d;
+}
+
 // exp(+2 pi i f_c (t - tau)) with the phase reduced in double-double.
 __device__ __forceinline__ void prephase(double t, double tau, double fch, double fcl,
                                          double& c, double& s) {

@@ -164,11 +164,11 @@ __global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
 // Binning.  bin_start[b] = index of the first point (in the order the spread
 // reads them) whose cell lies in bin b or later; bin_start[nbins] = nd.
 // ============================================================================
-__device__ __forceinline__ int64_t point_bin(double t, double tau, double df, const Plan& p) {
-  int64_t cell;
+__device__ __forceinline__ int point_bin(double t, double tau, double df, const Plan& p) {
+  int cell;
   double frac;
-  grid_coord(t, tau, df, (double)p.n, p.n, cell, frac);
-  return cell / p.Tb;
+  grid_coord32(t, tau, df, (double)p.n, (int)p.n, cell, frac);
+  return cell >> p.Tb_shift;
 }
 
 // Sorted fast path: the bins of consecutive points are non-decreasing, so the
@@ -180,8 +180,8 @@ __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Wo
   const double tau = st->tau;
   const int64_t nd = a.nd;
   const int64_t nb = p.nbins;
-  const int64_t kfirst = point_bin(a.t[0], tau, a.df, p);
-  const int64_t klast = point_bin(a.t[nd - 1], tau, a.df, p);
+  const int kfirst = point_bin(a.t[0], tau, a.df, p);
+  const int klast = point_bin(a.t[nd - 1], tau, a.df, p);
   const int64_t total = nd > nb + 1 ? nd : nb + 1;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kThreads) {
@@ -190,12 +190,12 @@ __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Wo
       else if (i > klast) w.bin_start[i] = (int)nd;
     }
     if (i >= 1 && i < nd) {
-      int64_t kp = point_bin(a.t[i - 1], tau, a.df, p);
-      int64_t kc = point_bin(a.t[i], tau, a.df, p);
+      const int kp = point_bin(a.t[i - 1], tau, a.df, p);
+      const int kc = point_bin(a.t[i], tau, a.df, p);
       if (kc < kp) {
         atomicOr(&w.stats->need_sort, 1);
       } else {
-        for (int64_t b = kp + 1; b <= kc; ++b) w.bin_start[b] = (int)i;
+        for (int b = kp + 1; b <= kc; ++b) w.bin_start[b] = (int)i;
       }
     }
   }
@@ -322,101 +322,82 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
 __device__ __forceinline__ int64_t floordiv2(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
 __device__ __forceinline__ int64_t ceildiv2(int64_t x) { return x >= 0 ? (x + 1) / 2 : -((-x) / 2); }
 
-struct PtRange {
-  int64_t b[4], e[4];
-  int n;
-};
-
-// Point ranges for the cyclic cell interval [c0, c1) (length < n) of the
-// binning geometry.
-__device__ __forceinline__ void add_cell_range(PtRange& r, int64_t c0, int64_t c1, const Plan& p,
-                                               const int* bs, int64_t nd) {
+// Append the point ranges of the cyclic cell interval [c0, c1) (of the
+// binning geometry) to rb/re (LDS arrays), at most two ranges.
+__device__ __forceinline__ void add_cell_range(int* rb, int* re, int& cnt, int64_t c0, int64_t c1,
+                                               const Plan& p, const int* bs, int nd) {
   const int64_t n = p.n;
   if (c1 - c0 >= n) {
-    r.b[r.n] = 0;
-    r.e[r.n] = nd;
-    r.n++;
+    rb[cnt] = 0;
+    re[cnt] = nd;
+    ++cnt;
     return;
   }
   int64_t x0 = c0 % n;
   if (x0 < 0) x0 += n;
-  int64_t x1 = x0 + (c1 - c0);
-  int64_t e1 = x1 <= n ? x1 : n;
-  r.b[r.n] = bs[x0 / p.Tb];
-  r.e[r.n] = bs[(e1 - 1) / p.Tb + 1];
-  r.n++;
+  const int64_t x1 = x0 + (c1 - c0);
+  const int64_t e1 = x1 <= n ? x1 : n;
+  rb[cnt] = bs[x0 >> p.Tb_shift];
+  re[cnt] = bs[((e1 - 1) >> p.Tb_shift) + 1];
+  ++cnt;
   if (x1 > n) {
-    r.b[r.n] = bs[0];
-    r.e[r.n] = bs[(x1 - n - 1) / p.Tb + 1];
-    r.n++;
+    rb[cnt] = bs[0];
+    re[cnt] = bs[((x1 - n - 1) >> p.Tb_shift) + 1];
+    ++cnt;
   }
 }
 
-// Points whose geometry-GEO coordinate may fall in the cyclic interval [c0, c1).
+// Points whose geometry-GEO coordinate may fall in the cyclic interval
+// [c0, c1); returns the number of ranges written (<= 4).
 template <int GEO>
-__device__ __forceinline__ void gather_ranges(PtRange& r, int64_t c0, int64_t c1, const Plan& p,
-                                              const int* bs, int64_t nd) {
-  r.n = 0;
+__device__ __forceinline__ int gather_ranges(int* rb, int* re, int64_t c0, int64_t c1,
+                                             const Plan& p, const int* bs, int nd) {
+  int cnt = 0;
   if (GEO == 1) {
-    add_cell_range(r, c0, c1, p, bs, nd);
+    add_cell_range(rb, re, cnt, c0, c1, p, bs, nd);
   } else {
     // u_2f = 2 u_f mod n: the cyclic interval [c0, c1) has the two pre-images
     // [c0/2, c1/2) and [(c0+n)/2, (c1+n)/2) in u_f (one cell of slack each side).
     if (c1 - c0 + 8 >= p.n) {
-      r.b[0] = 0;
-      r.e[0] = nd;
-      r.n = 1;
-      return;
+      rb[0] = 0;
+      re[0] = nd;
+      return 1;
     }
-    add_cell_range(r, floordiv2(c0) - 1, ceildiv2(c1) + 1, p, bs, nd);
-    add_cell_range(r, floordiv2(c0 + p.n) - 1, ceildiv2(c1 + p.n) + 1, p, bs, nd);
+    add_cell_range(rb, re, cnt, floordiv2(c0) - 1, ceildiv2(c1) + 1, p, bs, nd);
+    add_cell_range(rb, re, cnt, floordiv2(c0 + p.n) - 1, ceildiv2(c1 + p.n) + 1, p, bs, nd);
   }
+  return cnt;
 }
-
-__device__ __forceinline__ int64_t range_count(const PtRange& r) {
-  int64_t c = 0;
-  for (int i = 0; i < r.n; ++i) c += r.e[i] - r.b[i];
-  return c;
-}
-
-constexpr int kTileMax = 1024;
 
 template <typename Real, int GEO, int NG>
 __global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w, int gbase,
                                                      unsigned char* rowflag) {
   using T2 = typename cplx<Real>::T;
   __shared__ Real acc[NG][2][kTileMax];
-  __shared__ int64_t sb[4], se[4];
+  __shared__ int rb[8], re[8];
   __shared__ int snr, sactive;
   const DevStats* stp = w.stats;
   if (stp->status != 0) return;
   const int tid = threadIdx.x;
-  const int64_t tiles_per_row = p.S1 / p.T;
-  const int64_t ntiles = tiles_per_row * p.nrows;
-  const int64_t tile = xcd_remap(blockIdx.x, ntiles);
-  const int64_t row = tile / tiles_per_row;
-  const int64_t seg = tile - row * tiles_per_row;
-  const int64_t a0 = row * p.S1 + seg * p.T;
+  const int tiles_per_row = (int)(p.S1 / p.T);
+  const int ntiles = tiles_per_row * (int)p.nrows;
+  const int tile = (int)xcd_remap(blockIdx.x, ntiles);
+  const int row = tile / tiles_per_row;
+  const int seg = tile - row * tiles_per_row;
+  const int64_t a0 = (int64_t)row * p.S1 + (int64_t)seg * p.T;
   const int h = (int)ceil(p.hw) + 1;
-  const int64_t nd = a.nd;
-  const bool sorted = !stp->need_sort;
+  const int nd = (int)a.nd;
   const int* bs = w.bin_start;
 
   if (tid == 0) {
-    PtRange rr;
-    gather_ranges<GEO>(rr, row * p.S1 - h, (row + 1) * p.S1 + h, p, bs, nd);
-    int active = range_count(rr) > 0;
+    int cnt = gather_ranges<GEO>(rb, re, (int64_t)row * p.S1 - h, (int64_t)(row + 1) * p.S1 + h,
+                                 p, bs, nd);
+    int tot = 0;
+    for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
+    const int active = tot > 0;
     if (seg == 0) rowflag[row] = (unsigned char)active;
     sactive = active;
-    if (active) {
-      PtRange tr;
-      gather_ranges<GEO>(tr, a0 - h, a0 + p.T + h, p, bs, nd);
-      snr = tr.n;
-      for (int i = 0; i < tr.n; ++i) {
-        sb[i] = tr.b[i];
-        se[i] = tr.e[i];
-      }
-    }
+    snr = active ? gather_ranges<GEO>(rb, re, a0 - h, a0 + p.T + h, p, bs, nd) : 0;
   }
   __syncthreads();
   if (!sactive) return;
@@ -430,79 +411,78 @@ __global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w,
   }
   __syncthreads();
 
+  const bool sorted = !stp->need_sort;
   const double tau = stp->tau;
-  const double W = stp->W;
+  const double invW = 1.0 / stp->W;
   const double ysub = stp->ysub;
   const double gstep = GEO * a.df;
+  const int n = (int)p.n;
   const double nreal = (double)p.n;
   const int wd = p.w;
   const double hw = p.hw;
+  const double inv_hw = 1.0 / p.hw;
+  const Real beta = (Real)p.beta;
   // a kernel support can meet the tile at most once unless the tile spans
   // nearly the whole periodic grid
-  const bool wrap_free = (int64_t)T <= p.n - wd;
-  const Real beta = (Real)p.beta;
+  const bool wrap_free = T <= n - wd;
   const double* tt = sorted ? a.t : w.ts;
   const double* yy = a.periodogram ? (sorted ? a.y : w.ys) : (sorted ? a.h : w.hs);
   const double* dd = sorted ? a.dy : w.dys;
   const bool have_dy = a.periodogram && (sorted ? a.dy != nullptr : true);
-
-  int64_t off[5];
-  off[0] = 0;
-  for (int i = 0; i < snr; ++i) off[i + 1] = off[i] + (se[i] - sb[i]);
-  const int64_t npts = off[snr];
-  for (int64_t q = tid; q < npts; q += kThreads) {
-    int ri = 0;
-    while (q >= off[ri + 1]) ++ri;
-    const int64_t j = sb[ri] + (q - off[ri]);
-    const double t = tt[j];
-    int64_t cell;
-    double frac;
-    grid_coord(t, tau, gstep, nreal, p.n, cell, frac);
-    const int o0 = (int)ceil(frac - hw);
-    int64_t lb = (cell + o0 - a0) % p.n;
-    if (lb < 0) lb += p.n;
-    if (lb > p.n - wd) lb -= p.n;
-    if (wrap_free && (lb >= T || lb + wd <= 0)) continue;
-    // strengths
-    double pc, ps;
-    prephase(t, tau, a.fch, a.fcl, pc, ps);
-    Real hre[NG], him[NG];
-    if (a.periodogram) {
-      double wj = 1.0;
-      if (have_dy) {
-        double dv = dd[j];
-        wj = 1.0 / (dv * dv);
-      }
-      const double wh = wj / W;
-      if (GEO == 1) {
-        const double yt = yy[j] - ysub;
-        hre[0] = (Real)(wh * yt * pc);
-        him[0] = (Real)(wh * yt * ps);
-        if (NG > 1) {
-          hre[NG - 1] = (Real)(wh * pc);
-          him[NG - 1] = (Real)(wh * ps);
+  const int nr = snr;
+  for (int r = 0; r < nr; ++r) {
+    const int jend = re[r];
+    for (int j = rb[r] + tid; j < jend; j += kThreads) {
+      const double t = tt[j];
+      int cell;
+      double frac;
+      grid_coord32(t, tau, gstep, nreal, n, cell, frac);
+      const int o0 = (int)ceil(frac - hw);
+      int lb = cell + o0 - (int)a0;  // in (-2n, n)
+      if (lb < 0) lb += n;
+      if (lb < 0) lb += n;
+      if (lb > n - wd) lb -= n;
+      if (wrap_free && (lb >= T || lb + wd <= 0)) continue;
+      double pc, ps;
+      prephase(t, tau, a.fch, a.fcl, pc, ps);
+      Real hre[NG], him[NG];
+      if (a.periodogram) {
+        double wj = 1.0;
+        if (have_dy) {
+          const double dv = dd[j];
+          wj = 1.0 / (dv * dv);
+        }
+        const double wh = wj * invW;
+        if (GEO == 1) {
+          const double yt = yy[j] - ysub;
+          hre[0] = (Real)(wh * yt * pc);
+          him[0] = (Real)(wh * yt * ps);
+          if (NG > 1) {
+            hre[NG - 1] = (Real)(wh * pc);
+            him[NG - 1] = (Real)(wh * ps);
+          }
+        } else {
+          // exp(2 i theta) from exp(i theta)
+          hre[0] = (Real)(wh * (pc * pc - ps * ps));
+          him[0] = (Real)(wh * (2.0 * pc * ps));
         }
       } else {
-        // exp(2 i theta) from exp(i theta)
-        hre[0] = (Real)(wh * (pc * pc - ps * ps));
-        him[0] = (Real)(wh * (2.0 * pc * ps));
+        const double hv = yy[j];
+        hre[0] = (Real)(hv * pc);
+        him[0] = (Real)(hv * ps);
       }
-    } else {
-      const double hv = yy[j];
-      hre[0] = (Real)(hv * pc);
-      him[0] = (Real)(hv * ps);
-    }
-    for (int k = 0; k < wd; ++k) {
-      int64_t loc = lb + k;
-      if (loc < 0) loc += p.n;
-      else if (loc >= p.n) loc -= p.n;
-      if (loc >= T) continue;
-      const Real z = (Real)(((double)(o0 + k) - frac) / hw);
-      const Real v = es_kernel(z, beta);
+      for (int k = 0; k < wd; ++k) {
+        int loc = lb + k;
+        if (loc < 0) loc += n;
+        else if (loc >= n) loc -= n;
+        if (loc >= T) continue;
+        const Real z = (Real)(((double)(o0 + k) - frac) * inv_hw);
+        const Real v = es_kernel(z, beta);
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        atomicAdd(&acc[g][0][loc], v * hre[g]);
-        atomicAdd(&acc[g][1][loc], v * him[g]);
+        for (int g = 0; g < NG; ++g) {
+          atomicAdd(&acc[g][0][loc], v * hre[g]);
+          atomicAdd(&acc[g][1][loc], v * him[g]);
+        }
       }
     }
   }
@@ -522,8 +502,6 @@ __global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w,
 // ============================================================================
 // FFT passes.
 // ============================================================================
-constexpr int kLmax = 1024;
-
 template <typename Real>
 struct PassBufs {
   typename cplx<Real>::T* in[3];
@@ -531,21 +509,24 @@ struct PassBufs {
   const unsigned char* rowflag[3];
 };
 
-// A middle/first pass: workgroup = C consecutive columns s of one outer index
-// p; loads L x C elements (C contiguous per row), transforms along L in LDS,
-// applies the inter-pass twiddle and stores transposed.
-template <typename Real, int EMAX>
-__global__ __launch_bounds__(kThreads) void k_fft_pass(PassBufs<Real> b, FftPass ps,
-                                                       const typename cplx<Real>::T* tw,
-                                                       const DevStats* st) {
+// A first/middle pass: workgroup = C consecutive columns s of one outer index
+// p; loads L x C elements (C contiguous per row, 128-256 B segments),
+// transforms along L in LDS, applies the inter-pass twiddle and stores with
+// the outer index and k transposed.  Dynamic LDS: L*C elements + L twiddles
+// + L row flags.
+template <typename Real, int EMAX, int NT>
+__global__ __launch_bounds__(NT) void k_fft_pass(PassBufs<Real> b, FftPass ps,
+                                                 const typename cplx<Real>::T* tw,
+                                                 const DevStats* st) {
   using T2 = typename cplx<Real>::T;
-  __shared__ T2 buf[EMAX];
-  __shared__ T2 twL[kLmax];
-  __shared__ unsigned char rf[kLmax];
+  extern __shared__ __align__(16) unsigned char smem[];
   if (st->status != 0) return;
   const int g = blockIdx.y;
   const int tid = threadIdx.x;
-  const int L = ps.L, C = ps.C;
+  const int L = ps.L, C = ps.C, csh = ps.cshift;
+  T2* buf = reinterpret_cast<T2*>(smem);
+  T2* twL = buf + L * C;
+  unsigned char* rf = reinterpret_cast<unsigned char*>(twL + L);
   const int64_t S = ps.S, P = ps.P;
   const int64_t nsb = (S + C - 1) / C;
   const int64_t blk = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
@@ -555,35 +536,50 @@ __global__ __launch_bounds__(kThreads) void k_fft_pass(PassBufs<Real> b, FftPass
   const T2* in = b.in[g];
   T2* out = b.out[g];
   const unsigned char* rflag = b.rowflag[g];
-  for (int x = tid; x < L; x += kThreads) {
+  for (int x = tid; x < L; x += NT) {
     twL[x] = tw[ps.twL_off + x];
     rf[x] = rflag ? rflag[x] : (unsigned char)1;
   }
   __syncthreads();
   const int E = L * C;
   const int64_t inbase = pidx * (int64_t)L * S + s0;
-  for (int e = tid; e < E; e += kThreads) {
-    const int l = e / C;
-    const int c = e - l * C;
-    T2 v = czero<T2>();
-    if (c < ceff && rf[l]) v = in[inbase + (int64_t)l * S + c];
-    buf[e] = v;
+  constexpr int PER = (EMAX + NT - 1) / NT;
+  T2 v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    v[i] = czero<T2>();
+    if (e < E) {
+      const int l = e >> csh;
+      const int c = e & (C - 1);
+      if (c < ceff && rf[l]) v[i] = in[inbase + (int64_t)l * S + c];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < E) buf[e] = v[i];
   }
   __syncthreads();
-  lds_fft<EMAX, kThreads>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
+  lds_fft<EMAX, NT>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
   const int64_t mask = ((int64_t)1 << ps.bshift) - 1;
   const T2* tlo = tw + ps.twlo_off;
   const T2* thi = tw + ps.twhi_off;
   const int64_t PS = P * S;
-  for (int e = tid; e < E; e += kThreads) {
-    const int k = e / C;
-    const int c = e - k * C;
-    if (c >= ceff) continue;
-    const int64_t s = s0 + c;
-    T2 v = buf[e];
-    const int64_t x = s * k;
-    if (x) v = cmul(v, cmul(thi[x >> ps.bshift], tlo[x & mask]));
-    out[(int64_t)k * PS + pidx * S + s] = v;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < E) {
+      const int k = e >> csh;
+      const int c = e & (C - 1);
+      if (c < ceff) {
+        const int64_t s = s0 + c;
+        T2 x = buf[e];
+        const int64_t q = s * k;
+        if (q) x = cmul(x, cmul(thi[q >> ps.bshift], tlo[q & mask]));
+        out[(int64_t)k * PS + pidx * S + s] = x;
+      }
+    }
   }
 }
 
@@ -624,42 +620,52 @@ __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, doub
 // Last pass: D rows of length L per workgroup for the G grids, transformed in
 // LDS; output k of row p is the mode m = p + P k.  Deconvolution, crop to the
 // nf requested modes and (G = 3) the power are fused into the store.
-template <typename Real, int G, int EMAX>
-__global__ __launch_bounds__(kThreads) void k_fft_last(PassBufs<Real> b, FftPass ps, Plan pl,
-                                                       CallArgs a,
-                                                       const typename cplx<Real>::T* tw,
-                                                       const double* inv_phihat,
-                                                       const DevStats* stp) {
+// Dynamic LDS: G*D*(L+1) elements + L twiddles.
+template <typename Real, int G, int EMAX, int NT>
+__global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, Plan pl,
+                                                 CallArgs a, const typename cplx<Real>::T* tw,
+                                                 const double* inv_phihat, const DevStats* stp) {
   using T2 = typename cplx<Real>::T;
-  __shared__ T2 buf[EMAX];
-  __shared__ T2 twL[kLmax];
+  extern __shared__ __align__(16) unsigned char smem[];
   if (stp->status != 0) return;
   const int tid = threadIdx.x;
   const int L = ps.L, D = ps.C;
   const int Lp = L + 1;
+  T2* buf = reinterpret_cast<T2*>(smem);
+  T2* twL = buf + G * D * Lp;
   const int64_t P = ps.P;
   const int64_t nblk = (P + D - 1) / D;
   const int64_t blk = xcd_remap(blockIdx.x, nblk);
   const int64_t p0 = blk * D;
   const int deff = (int)((P - p0) < D ? (P - p0) : D);
-  for (int x = tid; x < L; x += kThreads) twL[x] = tw[ps.twL_off + x];
+  for (int x = tid; x < L; x += NT) twL[x] = tw[ps.twL_off + x];
   const int E = D * L;
+  constexpr int PER = (EMAX / G + NT - 1) / NT;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const T2* in = b.in[g] + p0 * (int64_t)L;
-    for (int e = tid; e < E; e += kThreads) {
-      const int d = e / L;
-      const int l = e - d * L;
-      T2 v = czero<T2>();
-      if (d < deff) v = in[e];
-      buf[(g * D + d) * Lp + l] = v;
+    T2 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      v[i] = czero<T2>();
+      if (e < E && e < deff * L) v[i] = in[e];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < E) {
+        const int d = e / L;
+        const int l = e - d * L;
+        buf[(g * D + d) * Lp + l] = v[i];
+      }
     }
   }
   __syncthreads();
-  lds_fft<EMAX, kThreads>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
+  lds_fft<EMAX, NT>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
   const DevStats st = *stp;
   const int64_t n = pl.n, nf = pl.nf, K = pl.K;
-  for (int e = tid; e < E; e += kThreads) {
+  for (int e = tid; e < E; e += NT) {
     const int d = e % D;
     const int k = e / D;
     if (d >= deff) continue;
@@ -720,6 +726,9 @@ template <typename Real>
 static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
                                 const StageHook* hook) {
   using T2 = typename cplx<Real>::T;
+  constexpr bool f64 = sizeof(Real) == 8;
+  constexpr int EMID = f64 ? kEmid64 : kEmid32;
+  constexpr int ELAST = f64 ? kElast64 : kElast32;
   const int G = a.periodogram ? 3 : 1;
   auto mark = [&](int stage, int begin) {
     if (hook) hook->fn(hook->ud, stage, begin, s);
@@ -730,13 +739,15 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   mark(kStageBin, 1);
   const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
   hipLaunchKernelGGL(k_bins_sorted, dim3(grid_for(nbt, 1 << 20)), dim3(kThreads), 0, s, a, p, w);
-  hipLaunchKernelGGL(k_sort_fill, dim3(grid_for(p.nbins + 1, 4096)), dim3(kThreads), 0, s, p, w);
-  hipLaunchKernelGGL(k_sort_hist, dim3(grid_for(a.nd, 4096)), dim3(kThreads), 0, s, a, p, w);
+  // counting-sort path: these exit at once unless a descent was found
+  const unsigned sort_blocks = grid_for(a.nd > p.nbins ? a.nd : p.nbins, 512);
+  hipLaunchKernelGGL(k_sort_fill, dim3(sort_blocks), dim3(kThreads), 0, s, p, w);
+  hipLaunchKernelGGL(k_sort_hist, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
   const int64_t nchunks = (p.nbins + 1 + kScanChunk - 1) / kScanChunk;
   hipLaunchKernelGGL(k_scan1, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
   hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kThreads), 0, s, nchunks, w);
   hipLaunchKernelGGL(k_scan3, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid_for(a.nd, 4096)), dim3(kThreads), 0, s, a, p, w);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
   mark(kStageBin, 0);
 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
@@ -772,10 +783,10 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.rowflag[g] = (ip == 0) ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
     }
     const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-    constexpr int EM = sizeof(Real) == 8 ? 4096 : 8192;
+    const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ps.L) + (size_t)ps.L + 16;
     mark(kStagePass0 + ip, 1);
-    hipLaunchKernelGGL((k_fft_pass<Real, EM>), dim3((unsigned)nblk, G), dim3(kThreads), 0, s, b,
-                       ps, tw, w.stats);
+    hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads>), dim3((unsigned)nblk, G),
+                       dim3(kThreads), lds, s, b, ps, tw, w.stats);
     mark(kStagePass0 + ip, 0);
     if (ip > 0) {
       for (int g = 0; g < 3; ++g) {
@@ -794,14 +805,14 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.rowflag[g] = nullptr;
     }
     const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
-    constexpr int EL = sizeof(Real) == 8 ? 3072 : 6144;
+    const size_t lds = sizeof(T2) * (size_t)(G * ps.C * (ps.L + 1) + ps.L);
     mark(kStageLast, 1);
     if (a.periodogram)
-      hipLaunchKernelGGL((k_fft_last<Real, 3, EL>), dim3((unsigned)nblk), dim3(kThreads), 0, s, b,
-                         ps, p, a, tw, w.inv_phihat, w.stats);
+      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, kThreadsLast>), dim3((unsigned)nblk),
+                         dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats);
     else
-      hipLaunchKernelGGL((k_fft_last<Real, 1, EL>), dim3((unsigned)nblk), dim3(kThreads), 0, s, b,
-                         ps, p, a, tw, w.inv_phihat, w.stats);
+      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, kThreadsLast>), dim3((unsigned)nblk),
+                         dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats);
     mark(kStageLast, 0);
   }
   return hipGetLastError();

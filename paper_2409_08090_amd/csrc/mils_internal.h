@@ -20,6 +20,7 @@ constexpr int kMaxRadixStages = 12;
 struct FftPass {
   int L;
   int C;                   // columns (S-direction) per workgroup; rows per workgroup in the last pass
+  int cshift;              // log2(C) for the first/middle passes (C is a power of two)
   int64_t P, S;
   int nrad;
   int rad[kMaxRadixStages];
@@ -44,7 +45,8 @@ struct Plan {
   int64_t S1;              // row length of the spreading view [n / S1][S1]
   int64_t nrows;           // n / S1
   int T;                   // spreading tile (divides S1)
-  int Tb;                  // bin width in cells
+  int Tb;                  // bin width in cells (a power of two)
+  int Tb_shift;            // log2(Tb)
   int64_t nbins;           // ceil(n / Tb)
   int D;                   // rows per workgroup of the last pass
   int64_t tw_count;        // complex entries in the twiddle buffer
@@ -106,6 +108,12 @@ struct Work {
 };
 
 constexpr int kStatsBlocks = 512;
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;       // threads of most kernels
+constexpr int kThreadsLast = 512;   // threads of the last FFT pass
+constexpr int kTileMax = 1024;      // spreading tile (cells)
+constexpr int kLmax = 1024;         // longest per-pass FFT length
+// elements held in LDS by one workgroup of a first/middle pass and of the last pass
+constexpr int kEmid64 = 2048, kEmid32 = 4096;
+constexpr int kElast64 = 3072, kElast32 = 6144;
 
 }  // namespace mils

@@ -17,11 +17,9 @@ namespace mils {
 
 namespace {
 
-constexpr int kTileMaxCells = 1024;   // spreading tile (LDS accumulator)
-constexpr int kMaxWidth = 16;         // widest spreading kernel
-constexpr int kLmaxPass = 1024;       // longest per-pass FFT length (twiddle LDS table)
-constexpr int kEmid64 = 4096, kEmid32 = 8192;     // elements per middle-pass workgroup
-constexpr int kElast64 = 3072, kElast32 = 6144;   // elements per last-pass workgroup
+constexpr int kTileMaxCells = kTileMax;  // spreading tile (LDS accumulator)
+constexpr int kMaxWidth = 20;            // widest spreading kernel
+constexpr int kLmaxPass = kLmax;         // longest per-pass FFT length
 
 std::vector<int64_t> smooth_in_range(int64_t lo, int64_t hi) {
   std::vector<int64_t> v;
@@ -116,20 +114,29 @@ bool split_mid(int64_t m, int k, int lmax, std::vector<int>* out) {
 
 double default_sigma(int prec) { return prec == 1 ? 1.5 : 1.25; }
 
+
+
+// Safety factor between the requested tolerance and the kernel's error
+// estimate.  The estimate exp(-pi w sqrt(1 - 1/sigma)) runs ~1.6x below the
+// measured worst-case error of the sums, and in FP64 the lowest frequencies of
+// a floating-mean periodogram (f span ~ 0.2, where the cos and sin columns are
+// nearly collinear) sit at the band edge of the transform and amplify it
+// further; FP32 accuracy is bounded by its rounding instead.
+static double width_margin(int prec) { return prec == 1 ? 2.0 : 8.0; }
+
+int kernel_width(double eps, double sigma, int prec) {
+  double w = std::ceil(std::log(width_margin(prec) / eps) /
+                       (M_PI * std::sqrt(1.0 - 1.0 / sigma)));
+  int wi = (int)w;
+  return std::min(kMaxWidth, std::max(2, wi));
+}
+
 // Upsampling factor for a tolerance: the precision's default, or 2 when the
 // default would need a kernel wider than kMaxWidth cells.
 static double choose_sigma(double eps, int prec) {
   const double s = default_sigma(prec);
-  const double w = std::log(2.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / s));
+  const double w = std::log(width_margin(prec) / eps) / (M_PI * std::sqrt(1.0 - 1.0 / s));
   return w > kMaxWidth ? 2.0 : s;
-}
-
-// The estimate exp(-pi w sqrt(1 - 1/sigma)) runs ~1.6x below the measured
-// worst-case error of the sums, so the width is sized for eps / 2.
-int kernel_width(double eps, double sigma) {
-  double w = std::ceil(std::log(2.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma)));
-  int wi = (int)w;
-  return std::min(kMaxWidth, std::max(2, wi));
 }
 
 double kernel_beta(int w, double sigma) { return 0.97 * M_PI * w * (1.0 - 1.0 / (2.0 * sigma)); }
@@ -140,14 +147,14 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   p.nf = r.nf;
   p.K = r.nf / 2;
   const double smin = r.sigma > 1.0 ? r.sigma : choose_sigma(r.eps, r.prec);
-  const int wguess = kernel_width(r.eps, smin);
+  const int wguess = kernel_width(r.eps, smin, r.prec);
   int64_t nmin = (int64_t)std::ceil(smin * (double)r.nf);
   nmin = std::max<int64_t>(nmin, 2 * wguess + 2);
   nmin = std::max<int64_t>(nmin, 16);
   const int G = r.G;
   const int emid = r.prec == 1 ? kEmid32 : kEmid64;
   const int elast = r.prec == 1 ? kElast32 : kElast64;
-  const int cmax = r.prec == 1 ? 32 : 16;
+  const int cmax = 32;
 
   auto cand = smooth_in_range(nmin, 2 * nmin + 64);
   double best_cost = 1e300;
@@ -193,7 +200,7 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   }
   p.n = best_n;
   p.sigma = (double)best_n / (double)r.nf;
-  p.w = kernel_width(r.eps, p.sigma);
+  p.w = kernel_width(r.eps, p.sigma, r.prec);
   // a grid that fits one workgroup costs nothing extra with the widest kernel,
   // and tiny problems (a handful of frequencies, huge sigma) need the margin:
   // the floating-mean cancellation at the lowest frequencies amplifies the
@@ -212,8 +219,10 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     ps.nrad = radix_plan(ps.L, ps.rad);
     if (i + 1 < best_np) {
       int c = std::min(cmax, pow2_floor(emid / ps.L));
-      if (ps.S < c) c = (int)std::max<int64_t>(1, ps.S);
+      while (c > 1 && c / 2 >= ps.S) c /= 2;
       ps.C = c;
+      ps.cshift = 0;
+      while ((1 << ps.cshift) < c) ++ps.cshift;
     } else {
       int d = 1;
       while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P) d *= 2;
@@ -236,6 +245,7 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     }
   p.T = T;
   p.Tb = best_n >= 4096 ? 32 : 8;
+  p.Tb_shift = best_n >= 4096 ? 5 : 3;
   p.nbins = (best_n + p.Tb - 1) / p.Tb;
   if (out) *out = p;
   return true;

@@ -23,8 +23,8 @@ struct PlanRequest {
 // Default upsampling factor of a precision.
 double default_sigma(int prec);
 
-// Kernel width for tolerance eps at upsampling sigma (clamped to [2, 16]).
-int kernel_width(double eps, double sigma);
+// Kernel width for tolerance eps at upsampling sigma (clamped to [2, 20]).
+int kernel_width(double eps, double sigma, int prec);
 
 // Shape parameter of the exponential-of-semicircle kernel.
 double kernel_beta(int w, double sigma);
