@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--nd", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -174,6 +175,28 @@ def main():
         ms32 = (a1 - a0) * 1e3 / args.steps
         extra["fp32_form"] = {"ms_per_step": round(ms32, 4), "value": sums / (ms32 * 1e-3),
                               "eps": 1e-5}
+
+    # batched form: 10,000 series in one persistent launch, FP64 and FP32
+    if not args.no_batch:
+        curves = workloads.batch(seed=3)
+        bt, by, bdy, nd_off, nf_off, f0s, dfs = mils.pack_curves(curves, device=dev)
+        bout = torch.empty(int(nf_off[-1]), dtype=torch.float64, device=dev)
+        bsums = float(sum(float(c.nd) * float(c.nf) for c in curves))
+        extra["batch"] = {"ncurves": len(curves), "sum_nd_nf": bsums}
+        for prec, e in (("fp64", 1e-9), ("fp32", 1e-5)):
+            for _ in range(2):
+                mils.periodogram_batch(bt, by, bdy, nd_off, nf_off, f0s, dfs, eps=e,
+                                       precision=prec, out=bout, ctx=ctx, stream=stream)
+            torch.cuda.synchronize()
+            b0 = time.perf_counter()
+            nb = max(3, args.steps // 4)
+            for _ in range(nb):
+                mils.periodogram_batch(bt, by, bdy, nd_off, nf_off, f0s, dfs, eps=e,
+                                       precision=prec, out=bout, ctx=ctx, stream=stream)
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - b0) * 1e3 / nb
+            extra["batch"][prec] = {"ms_per_batch": round(bms, 3),
+                                    "value": bsums / (bms * 1e-3), "eps": e}
 
     cpu = None
     if not args.no_cpu_baseline:

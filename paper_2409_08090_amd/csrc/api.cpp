@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "../../include/mils.h"
+#include "batch.h"
 #include "kernels.h"
 #include "mils_internal.h"
 #include "plan.h"
@@ -28,7 +30,8 @@ struct PlanEntry {
   size_t bytes = 0;
 };
 
-using PlanKey = std::tuple<int64_t, double, int, int, double>;
+// (nf, eps, precision, grids + 10 * batch, fixed grid size)
+using PlanKey = std::tuple<int64_t, double, int, int, int64_t>;
 
 std::mutex g_err_mu;
 std::string g_create_err;
@@ -39,6 +42,59 @@ void host_dd_sum(double a, double b, double* s, double* e) {
   *e = (a - (x - bb)) + (b - bb);
   *s = x;
 }
+
+// f_c = f0 + K df as a double-double (K df is exact as a two-product)
+void centre_frequency(double f0, double df, int64_t K, double* fch, double* fcl) {
+  const double Kd = (double)K;
+  const double prod = Kd * df;
+  const double perr = std::fma(Kd, df, -prod);
+  double s, e;
+  host_dd_sum(f0, prod, &s, &e);
+  *fch = s;
+  *fcl = e + perr;
+}
+
+// output index of the zero frequency: the k whose binary64 frequency
+// fl(f0 + fl(k df)) is zero, or -1
+int64_t zero_index(double f0, double df, int64_t nf) {
+  const double kq = std::nearbyint(-f0 / df);
+  int64_t kz = -1;
+  for (double kk = kq - 1; kk <= kq + 1; kk += 1.0)
+    if (kk >= 0.0 && kk < (double)nf && kk * df == -f0) kz = (int64_t)kk;
+  return kz;
+}
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// State of the batched path kept between calls: the uploaded descriptors, the
+// slot workspace and the captured graph are reused when the next batch has
+// the same layout and parameters.
+struct BatchState {
+  uint64_t key = 0;
+  bool valid = false;
+  char* dev = nullptr;  // descriptors, plans, table pointers, status, counter
+  size_t dev_bytes = 0;
+  char* ws = nullptr;   // slot workspaces
+  size_t ws_bytes = 0;
+  int nslots = 0;
+  int prec = 0;
+  int64_t ncurves = 0;
+  mils::BatchArgs args{};
+  int* status_dev = nullptr;
+  int32_t* status_host = nullptr;  // pinned
+  size_t status_cap = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::map<std::tuple<int64_t, int, double>, int64_t> grid_of_nf;  // (nf, prec, eps) -> grid size
+};
 
 }  // namespace
 
@@ -60,6 +116,8 @@ struct mils_context {
   hipEvent_t prof_begin[kNumStages] = {};
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_recs;
   std::vector<hipEvent_t> prof_pool;
+  int num_cu = 256;
+  BatchState batch;
 };
 
 namespace {
@@ -99,8 +157,8 @@ int check_nd(int64_t nd) {
 }
 
 int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEntry** out,
-             bool upload) {
-  PlanKey key{nf, eps, prec, G, 0.0};
+             bool upload, bool batch = false, int64_t n_fixed = 0) {
+  PlanKey key{nf, eps, prec, G + (batch ? 10 : 0), n_fixed};
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end() && (!upload || it->second.tw)) {
     *out = &it->second;
@@ -109,6 +167,8 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   PlanEntry e;
   std::string err;
   PlanRequest r{nf, eps, prec, G};
+  r.batch = batch;
+  r.n_fixed = n_fixed;
   if (!make_plan(r, &e.plan, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
   std::vector<double> tw;
   make_twiddles(&e.plan, &tw);
@@ -234,26 +294,11 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.dy = dy;
   a.h = h;
   a.nd = nd;
+  a.nf = p->nf;
   a.f0 = p->f0;
   a.df = p->df;
-  // f_c = f0 + K df as a double-double (K df is exact as a two-product)
-  {
-    const double Kd = (double)plan.K;
-    double prod = Kd * p->df;
-    double perr = std::fma(Kd, p->df, -prod);
-    double s, e;
-    host_dd_sum(p->f0, prod, &s, &e);
-    a.fch = s;
-    a.fcl = e + perr;
-  }
-  // output index of the zero frequency: the k whose binary64 frequency
-  // fl(f0 + fl(k df)) is zero
-  a.kzero = -1;
-  {
-    double kq = std::nearbyint(-p->f0 / p->df);
-    for (double kk = kq - 1; kk <= kq + 1; kk += 1.0)
-      if (kk >= 0.0 && kk < (double)p->nf && kk * p->df == -p->f0) a.kzero = (int64_t)kk;
-  }
+  centre_frequency(p->f0, p->df, plan.K, &a.fch, &a.fcl);
+  a.kzero = zero_index(p->f0, p->df, p->nf);
   a.norm = p->normalization;
   a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
   a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
@@ -318,6 +363,8 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
     }
     he = hipSetDevice(device);
     if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), 64);
+    if (he == hipSuccess)
+      he = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (he != hipSuccess) {
       std::lock_guard<std::mutex> lk(g_err_mu);
       g_create_err = std::string("context init: ") + hipGetErrorString(he);
@@ -337,6 +384,13 @@ int mils_context_destroy(mils_context* ctx) {
     for (auto& kv : ctx->plans)
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
+    BatchState& b = ctx->batch;
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    if (b.cap_stream) (void)hipStreamDestroy(b.cap_stream);
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.ws) (void)hipFree(b.ws);
+    if (b.status_host) (void)hipHostFree(b.status_host);
     if (ctx->host_status) (void)hipHostFree(ctx->host_status);
     for (auto& r : ctx->prof_recs) {
       (void)hipEventDestroy(std::get<1>(r));
@@ -416,7 +470,8 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
                            const mils_params* common, double* power, int32_t* status_per_curve,
                            void* hip_stream) {
   if (!ctx) return MILS_ERR_INVALID_ARG;
-  if (ncurves < 1 || !nd_off || !nf_off || !f0 || !df || !common || !t || !y || !power)
+  if (ncurves < 1 || ncurves > (int64_t)0x7fffffff || !nd_off || !nf_off || !f0 || !df ||
+      !common || !t || !y || !power)
     return fail(ctx, MILS_ERR_INVALID_ARG, "invalid batch arguments");
   if (nd_off[0] != 0 || nf_off[0] != 0) return fail(ctx, MILS_ERR_INVALID_ARG, "offsets must start at 0");
   for (int64_t c = 0; c < ncurves; ++c) {
@@ -426,22 +481,224 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
     p.nf = nf_off[c + 1] - nf_off[c];
     int rc = check_nd(nd_off[c + 1] - nd_off[c]);
     if (rc == MILS_OK) rc = check_params(&p);
-    if (rc != MILS_OK) return fail(ctx, rc, "invalid curve in batch");
+    if (rc != MILS_OK) return fail(ctx, rc, "invalid curve " + std::to_string(c) + " in batch");
   }
+  if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  BatchState& B = ctx->batch;
+  const int prec = common->precision;
+
+  uint64_t key = 1469598103934665603ull;
+  key = fnv1a(key, &ncurves, sizeof(ncurves));
+  key = fnv1a(key, nd_off, sizeof(int64_t) * (ncurves + 1));
+  key = fnv1a(key, nf_off, sizeof(int64_t) * (ncurves + 1));
+  key = fnv1a(key, f0, sizeof(double) * ncurves);
+  key = fnv1a(key, df, sizeof(double) * ncurves);
+  key = fnv1a(key, &common->eps, sizeof(double));
+  key = fnv1a(key, &common->precision, sizeof(int32_t) * 2);
+  key = fnv1a(key, &common->flags, sizeof(uint32_t));
+  const void* ptrs[4] = {t, y, dy, power};
+  key = fnv1a(key, ptrs, sizeof(ptrs));
+
+  if (!(B.valid && B.key == key)) {
+    B.valid = false;
+    // grid size of each series, then grid-size classes (ratio <= 1.06) that share a plan
+    std::vector<int64_t> ngrid(ncurves);
+    for (int64_t c = 0; c < ncurves; ++c) {
+      const int64_t nf = nf_off[c + 1] - nf_off[c];
+      auto k = std::make_tuple(nf, prec, common->eps);
+      auto it = B.grid_of_nf.find(k);
+      if (it == B.grid_of_nf.end()) {
+        Plan pl;
+        std::string err;
+        PlanRequest r{nf, common->eps, prec, 3};
+        r.batch = true;
+        if (!make_plan(r, &pl, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
+        it = B.grid_of_nf.emplace(k, pl.n).first;
+      }
+      ngrid[c] = it->second;
+    }
+    std::vector<int64_t> ns(ngrid);
+    std::sort(ns.begin(), ns.end());
+    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+    std::map<int64_t, int> cls_of_n;
+    std::vector<int64_t> cls_n;
+    for (size_t i = 0; i < ns.size();) {
+      size_t j = i;
+      while (j + 1 < ns.size() && (double)ns[j + 1] <= 1.06 * (double)ns[i]) ++j;
+      const int cid = (int)cls_n.size();
+      cls_n.push_back(ns[j]);
+      for (size_t q = i; q <= j; ++q) cls_of_n[ns[q]] = cid;
+      i = j + 1;
+    }
+    const int ncls = (int)cls_n.size();
+    std::vector<int64_t> cls_nf(ncls, 1);
+    std::vector<int> cls_of(ncurves);
+    for (int64_t c = 0; c < ncurves; ++c) {
+      cls_of[c] = cls_of_n[ngrid[c]];
+      cls_nf[cls_of[c]] = std::max<int64_t>(cls_nf[cls_of[c]], nf_off[c + 1] - nf_off[c]);
+    }
+    std::vector<Plan> plans(ncls);
+    std::vector<const void*> twp(ncls);
+    std::vector<const double*> php(ncls);
+    Plan big{};
+    int64_t nd_max = 1;
+    for (int k = 0; k < ncls; ++k) {
+      PlanEntry* pe = nullptr;
+      int rc = get_plan(ctx, cls_nf[k], common->eps, prec, 3, &pe, true, true, cls_n[k]);
+      if (rc != MILS_OK) return rc;
+      plans[k] = pe->plan;
+      twp[k] = pe->tw;
+      php[k] = pe->inv_phihat;
+      const Plan& q = pe->plan;
+      big.prec = prec;
+      big.n = std::max(big.n, q.n);
+      big.nbins = std::max(big.nbins, q.nbins);
+      big.nrows = std::max(big.nrows, q.nrows);
+      big.npass = std::max(big.npass, q.npass);
+    }
+    for (int64_t c = 0; c < ncurves; ++c) nd_max = std::max(nd_max, nd_off[c + 1] - nd_off[c]);
+    // descriptors ordered by decreasing estimated cost
+    std::vector<BatchCurve> cur(ncurves);
+    for (int64_t c = 0; c < ncurves; ++c) {
+      BatchCurve& d = cur[c];
+      const Plan& q = plans[cls_of[c]];
+      d.t_off = nd_off[c];
+      d.nd = nd_off[c + 1] - nd_off[c];
+      d.out_off = nf_off[c];
+      d.nf = nf_off[c + 1] - nf_off[c];
+      d.K = d.nf / 2;
+      d.f0 = f0[c];
+      d.df = df[c];
+      centre_frequency(d.f0, d.df, d.K, &d.fch, &d.fcl);
+      d.kzero = zero_index(d.f0, d.df, d.nf);
+      d.plan = cls_of[c];
+      d.index = (int)c;
+      (void)q;
+    }
+    std::vector<double> cost(ncurves);
+    for (int64_t c = 0; c < ncurves; ++c) {
+      const Plan& q = plans[cls_of[c]];
+      cost[c] = (double)q.n * (2.0 * q.npass + 1.0) * 3.0 + (double)cur[c].nd * q.w * 3.0;
+    }
+    std::vector<int64_t> order(ncurves);
+    for (int64_t c = 0; c < ncurves; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    std::vector<BatchCurve> sorted(ncurves);
+    for (int64_t i = 0; i < ncurves; ++i) sorted[i] = cur[order[i]];
+
+    // device buffers
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_cur = 0;
+    const size_t o_plan = o_cur + al(sizeof(BatchCurve) * ncurves);
+    const size_t o_tw = o_plan + al(sizeof(Plan) * ncls);
+    const size_t o_ph = o_tw + al(sizeof(void*) * ncls);
+    const size_t o_st = o_ph + al(sizeof(void*) * ncls);
+    const size_t o_cnt = o_st + al(sizeof(int) * ncurves);
+    const size_t dev_bytes = o_cnt + 256;
+    const size_t slot_bytes = layout_work(big, nd_max, 3, nullptr, nullptr);
+    const int nslots = (int)std::min<int64_t>(ncurves, 2 * (int64_t)ctx->num_cu);
+    const size_t ws_bytes = slot_bytes * nslots;
+    if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_bytes > ctx->budget)
+      return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
+    he = hipStreamSynchronize(stream);
+    if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
+    if (B.dev_bytes < dev_bytes) {
+      if (B.dev) (void)hipFree(B.dev);
+      B.dev = nullptr;
+      B.dev_bytes = 0;
+      if (hipMalloc(&B.dev, dev_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch descriptors failed");
+      }
+      B.dev_bytes = dev_bytes;
+    }
+    if (B.ws_bytes < ws_bytes) {
+      if (B.ws) (void)hipFree(B.ws);
+      B.ws = nullptr;
+      B.ws_bytes = 0;
+      if (hipMalloc(&B.ws, ws_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch workspace failed");
+      }
+      B.ws_bytes = ws_bytes;
+    }
+    if (B.status_cap < (size_t)ncurves) {
+      if (B.status_host) (void)hipHostFree(B.status_host);
+      B.status_host = nullptr;
+      he = hipHostMalloc(reinterpret_cast<void**>(&B.status_host), sizeof(int32_t) * ncurves);
+      if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "pinned status buffer");
+      B.status_cap = ncurves;
+    }
+    he = hipMemcpy(B.dev + o_cur, sorted.data(), sizeof(BatchCurve) * ncurves, hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = hipMemcpy(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls, hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = hipMemcpy(B.dev + o_tw, twp.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = hipMemcpy(B.dev + o_ph, php.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
+    BatchArgs ba{};
+    ba.curves = reinterpret_cast<const BatchCurve*>(B.dev + o_cur);
+    ba.ncurves = (int)ncurves;
+    ba.plans = reinterpret_cast<const Plan*>(B.dev + o_plan);
+    ba.tw = reinterpret_cast<const void* const*>(B.dev + o_tw);
+    ba.inv_phihat = reinterpret_cast<const double* const*>(B.dev + o_ph);
+    ba.t = t;
+    ba.y = y;
+    ba.dy = dy;
+    ba.power = power;
+    ba.norm = common->normalization;
+    ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
+    ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
+    ba.counter = reinterpret_cast<unsigned int*>(B.dev + o_cnt);
+    ba.status = reinterpret_cast<int*>(B.dev + o_st);
+    layout_work(big, nd_max, 3, B.ws, &ba.w0);
+    ba.slot_stride = slot_bytes;
+    B.status_dev = ba.status;
+    // slot statistics blocks hold no counters, nothing to clear
+    // capture the launch (queue reset + persistent kernel) as a graph
+    if (B.exec) (void)hipGraphExecDestroy(B.exec);
+    if (B.graph) (void)hipGraphDestroy(B.graph);
+    B.exec = nullptr;
+    B.graph = nullptr;
+    if (!B.cap_stream) {
+      he = hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking);
+      if (he != hipSuccess) return hip_fail(ctx, he, "capture stream");
+    }
+    he = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      hipError_t le = launch_batch(ba, nslots, prec, B.cap_stream);
+      he = hipStreamEndCapture(B.cap_stream, &B.graph);
+      if (le != hipSuccess) he = le;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) return hip_fail(ctx, he, "batch graph capture");
+    B.args = ba;
+    B.nslots = nslots;
+    B.prec = prec;
+    B.ncurves = ncurves;
+    B.key = key;
+    B.valid = true;
+  }
+  he = hipGraphLaunch(B.exec, stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(B.status_host, B.status_dev, sizeof(int32_t) * ncurves,
+                        hipMemcpyDeviceToHost, stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(stream);
+  if (he != hipSuccess) return hip_fail(ctx, he, "batch launch");
   int worst = MILS_OK;
   for (int64_t c = 0; c < ncurves; ++c) {
-    mils_params p = *common;
-    p.f0 = f0[c];
-    p.df = df[c];
-    p.nf = nf_off[c + 1] - nf_off[c];
-    const int64_t o = nd_off[c];
-    int rc = run_single(ctx, t + o, y + o, dy ? dy + o : nullptr, nullptr, nd_off[c + 1] - o, &p,
-                        power + nf_off[c], nullptr, reinterpret_cast<hipStream_t>(hip_stream),
-                        true);
-    if (rc == MILS_ERR_DEVICE || rc == MILS_ERR_OOM || rc == MILS_ERR_UNSUPPORTED) return rc;
+    int st = B.status_host[c];
+    int rc = st == -1 ? MILS_ERR_INVALID_ARG : st == -2 ? MILS_ERR_DEGENERATE : MILS_OK;
     if (status_per_curve) status_per_curve[c] = rc;
-    if (rc != MILS_OK) worst = rc;
+    if (rc != MILS_OK && worst == MILS_OK) worst = rc;
   }
+  if (worst != MILS_OK) ctx->err = "some series of the batch have invalid or constant data";
   return worst;
 }
 

@@ -67,7 +67,8 @@ struct DevStats {
   int need_sort;   // points must go through the counting sort
   int status;      // 0 ok, -1 invalid input, -2 degenerate (YY == 0)
   unsigned int done;  // last-block counter of the reduction (self-resetting)
-  int pad[3];
+  int nlow;        // frequencies evaluated directly near f = 0 (see lowfix)
+  int64_t k_lo;    // first of them
 };
 
 // Per-call description of the data and output.
@@ -77,6 +78,7 @@ struct CallArgs {
   const double* dy;   // NULL = unit weights
   const double* h;    // raw trig sums strengths (NULL for periodograms)
   int64_t nd;
+  int64_t nf;         // number of output frequencies
   double f0, df;
   double fch, fcl;    // f0 + K df as an unevaluated double-double
   int64_t kzero;      // output index with f == 0 exactly, or -1
@@ -105,6 +107,8 @@ struct Work {
   void* grid2[3];         // second buffers for passes >= 2
   const void* tw;         // twiddles (plan-owned)
   const double* inv_phihat;  // 1 / phihat(|m|), m = 0..K (plan-owned)
+  double* lowpart;        // per-block partial direct sums near f = 0
+  double* lowfix;         // direct sums A, B, B2 near f = 0 (kLowMax x 6)
 };
 
 constexpr int kStatsBlocks = 512;
@@ -115,5 +119,15 @@ constexpr int kLmax = 1024;         // longest per-pass FFT length
 // elements held in LDS by one workgroup of a first/middle pass and of the last pass
 constexpr int kEmid64 = 2048, kEmid32 = 4096;
 constexpr int kElast64 = 3072, kElast32 = 6144;
+// the persistent batched kernel runs every phase with 256 threads
+constexpr int kElastBatch64 = 1536, kElastBatch32 = 3072;
+constexpr int kBatchLds = 65536;    // dynamic LDS of the batched kernel
+// Near f = 0 (|f| * span < 2) the floating-mean terms CC = (1 + C2)/2 - C^2 etc.
+// cancel and the 2x2 fit is ill-conditioned; there the three sums are
+// evaluated directly (FP64, at most kLowMax frequencies) instead of read
+// from the transform's band edge.
+constexpr int kLowMax = 16;
+constexpr int kLowGroup = 8;
+constexpr int kLowBlocks = 256;
 
 }  // namespace mils

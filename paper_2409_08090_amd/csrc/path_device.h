@@ -1,0 +1,521 @@
+// path_device.h -- device-side building blocks of the NUFFT Lomb-Scargle
+// path, shared by the single-series kernels (kernels.hip) and the persistent
+// batched kernel (batch.hip): moment merging, point binning, tile spreading,
+// one workgroup's share of an FFT pass, and the power assembly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "fft_core.h"
+#include "mils_internal.h"
+
+namespace mils {
+
+struct Moments {
+  double W, mu, M2;
+};
+
+__device__ __forceinline__ void moments_merge(Moments& a, double Wb, double mub, double M2b) {
+  double W = a.W + Wb;
+  if (W == 0.0) return;
+  double d = mub - a.mu;
+  double fb = Wb / W;
+  a.mu += d * fb;
+  a.M2 += M2b + d * d * a.W * fb;
+  a.W = W;
+}
+
+
+__device__ __forceinline__ int point_bin(double t, double tau, double df, const Plan& p) {
+  int cell;
+  double frac;
+  grid_coord32(t, tau, df, (double)p.n, (int)p.n, cell, frac);
+  return cell >> p.Tb_shift;
+}
+
+
+constexpr int kScanChunk = 2048;  // 256 threads x 8
+
+
+__device__ __forceinline__ int64_t floordiv2(int64_t x) { return x >= 0 ? x / 2 : -((-x + 1) / 2); }
+__device__ __forceinline__ int64_t ceildiv2(int64_t x) { return x >= 0 ? (x + 1) / 2 : -((-x) / 2); }
+
+// Append the point ranges of the cyclic cell interval [c0, c1) (of the
+// binning geometry) to rb/re (LDS arrays), at most two ranges.
+__device__ __forceinline__ void add_cell_range(int* rb, int* re, int& cnt, int64_t c0, int64_t c1,
+                                               const Plan& p, const int* bs, int nd) {
+  const int64_t n = p.n;
+  if (c1 - c0 >= n) {
+    rb[cnt] = 0;
+    re[cnt] = nd;
+    ++cnt;
+    return;
+  }
+  int64_t x0 = c0 % n;
+  if (x0 < 0) x0 += n;
+  const int64_t x1 = x0 + (c1 - c0);
+  const int64_t e1 = x1 <= n ? x1 : n;
+  rb[cnt] = bs[x0 >> p.Tb_shift];
+  re[cnt] = bs[((e1 - 1) >> p.Tb_shift) + 1];
+  ++cnt;
+  if (x1 > n) {
+    rb[cnt] = bs[0];
+    re[cnt] = bs[((x1 - n - 1) >> p.Tb_shift) + 1];
+    ++cnt;
+  }
+}
+
+// Points whose geometry-GEO coordinate may fall in the cyclic interval
+// [c0, c1); returns the number of ranges written (<= 4).
+template <int GEO>
+__device__ __forceinline__ int gather_ranges(int* rb, int* re, int64_t c0, int64_t c1,
+                                             const Plan& p, const int* bs, int nd) {
+  int cnt = 0;
+  if (GEO == 1) {
+    add_cell_range(rb, re, cnt, c0, c1, p, bs, nd);
+  } else {
+    // u_2f = 2 u_f mod n: the cyclic interval [c0, c1) has the two pre-images
+    // [c0/2, c1/2) and [(c0+n)/2, (c1+n)/2) in u_f (one cell of slack each side).
+    if (c1 - c0 + 8 >= p.n) {
+      rb[0] = 0;
+      re[0] = nd;
+      return 1;
+    }
+    add_cell_range(rb, re, cnt, floordiv2(c0) - 1, ceildiv2(c1) + 1, p, bs, nd);
+    add_cell_range(rb, re, cnt, floordiv2(c0 + p.n) - 1, ceildiv2(c1 + p.n) + 1, p, bs, nd);
+  }
+  return cnt;
+}
+
+// Spread one tile (T cells starting at tile*T of the [nrows][S1] view) of
+// geometry GEO into NG grids.  acc: LDS accumulator of NG*2*kTileMax Reals;
+// rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by every thread of the
+// workgroup (it contains barriers).
+template <typename Real, int GEO, int NG, int NT>
+__device__ void spread_tile(int tile, const CallArgs& a, const Plan& p, const Work& w,
+                            const DevStats& st, int gbase, unsigned char* rowflag, Real* acc,
+                            int* rb, int* re, int* sv) {
+  using T2 = typename cplx<Real>::T;
+  const int tid = threadIdx.x;
+  const int tiles_per_row = (int)(p.S1 / p.T);
+  const int row = tile / tiles_per_row;
+  const int seg = tile - row * tiles_per_row;
+  const int64_t a0 = (int64_t)row * p.S1 + (int64_t)seg * p.T;
+  const int h = (int)ceil(p.hw) + 1;
+  const int nd = (int)a.nd;
+  const int* bs = w.bin_start;
+  if (tid == 0) {
+    int cnt = gather_ranges<GEO>(rb, re, (int64_t)row * p.S1 - h, (int64_t)(row + 1) * p.S1 + h,
+                                 p, bs, nd);
+    int tot = 0;
+    for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
+    const int active = tot > 0;
+    if (seg == 0) rowflag[row] = (unsigned char)active;
+    sv[1] = active;
+    sv[0] = active ? gather_ranges<GEO>(rb, re, a0 - h, a0 + p.T + h, p, bs, nd) : 0;
+  }
+  __syncthreads();
+  const int active = sv[1];
+  const int nr = sv[0];
+  if (!active) {
+    __syncthreads();  // sv/rb/re are reused by the next tile
+    return;
+  }
+  const int T = p.T;
+  for (int x = tid; x < T; x += NT) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      acc[(2 * g) * kTileMax + x] = 0;
+      acc[(2 * g + 1) * kTileMax + x] = 0;
+    }
+  }
+  __syncthreads();
+
+  const bool sorted = !st.need_sort;
+  const double tau = st.tau;
+  const double invW = 1.0 / st.W;
+  const double ysub = st.ysub;
+  const double gstep = GEO * a.df;
+  const int n = (int)p.n;
+  const double nreal = (double)p.n;
+  const int wd = p.w;
+  const double hw = p.hw;
+  const double inv_hw = 1.0 / p.hw;
+  const Real beta = (Real)p.beta;
+  // a kernel support can meet the tile at most once unless the tile spans
+  // nearly the whole periodic grid
+  const bool wrap_free = T <= n - wd;
+  const double* tt = sorted ? a.t : w.ts;
+  const double* yy = a.periodogram ? (sorted ? a.y : w.ys) : (sorted ? a.h : w.hs);
+  const double* dd = sorted ? a.dy : w.dys;
+  const bool have_dy = a.periodogram && (sorted ? a.dy != nullptr : true);
+  for (int r = 0; r < nr; ++r) {
+    const int jend = re[r];
+    for (int j = rb[r] + tid; j < jend; j += NT) {
+      const double t = tt[j];
+      int cell;
+      double frac;
+      grid_coord32(t, tau, gstep, nreal, n, cell, frac);
+      const int o0 = (int)ceil(frac - hw);
+      int lb = cell + o0 - (int)a0;  // in (-2n, n)
+      if (lb < 0) lb += n;
+      if (lb < 0) lb += n;
+      if (lb > n - wd) lb -= n;
+      if (wrap_free && (lb >= T || lb + wd <= 0)) continue;
+      double pc, ps;
+      prephase(t, tau, a.fch, a.fcl, pc, ps);
+      Real hre[NG], him[NG];
+      if (a.periodogram) {
+        double wj = 1.0;
+        if (have_dy) {
+          const double dv = dd[j];
+          wj = 1.0 / (dv * dv);
+        }
+        const double wh = wj * invW;
+        if (GEO == 1) {
+          const double yt = yy[j] - ysub;
+          hre[0] = (Real)(wh * yt * pc);
+          him[0] = (Real)(wh * yt * ps);
+          if (NG > 1) {
+            hre[NG - 1] = (Real)(wh * pc);
+            him[NG - 1] = (Real)(wh * ps);
+          }
+        } else {
+          // exp(2 i theta) from exp(i theta)
+          hre[0] = (Real)(wh * (pc * pc - ps * ps));
+          him[0] = (Real)(wh * (2.0 * pc * ps));
+        }
+      } else {
+        const double hv = yy[j];
+        hre[0] = (Real)(hv * pc);
+        him[0] = (Real)(hv * ps);
+      }
+      for (int k = 0; k < wd; ++k) {
+        int loc = lb + k;
+        if (loc < 0) loc += n;
+        else if (loc >= n) loc -= n;
+        if (loc >= T) continue;
+        const Real z = (Real)(((double)(o0 + k) - frac) * inv_hw);
+        const Real v = es_kernel(z, beta);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          atomicAdd(&acc[(2 * g) * kTileMax + loc], v * hre[g]);
+          atomicAdd(&acc[(2 * g + 1) * kTileMax + loc], v * him[g]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    T2* out = reinterpret_cast<T2*>(w.grid[gbase + g]);
+    for (int x = tid; x < T; x += NT) {
+      T2 v;
+      v.x = acc[(2 * g) * kTileMax + x];
+      v.y = acc[(2 * g + 1) * kTileMax + x];
+      out[a0 + x] = v;
+    }
+  }
+  __syncthreads();
+}
+
+
+template <typename Real>
+struct PassBufs {
+  typename cplx<Real>::T* in[3];
+  typename cplx<Real>::T* out[3];
+  const unsigned char* rowflag[3];
+};
+
+// A first/middle pass: workgroup = C consecutive columns s of one outer index
+// p; loads L x C elements (C contiguous per row, 128-256 B segments),
+// transforms along L in LDS, applies the inter-pass twiddle and stores with
+// the outer index and k transposed.  Dynamic LDS: L*C elements + L twiddles
+// + L row flags.
+// One workgroup's share of a first/middle pass: logical block blk of grid g.
+// smem: L*C elements + L twiddles + L row flags.
+template <typename Real, int EMAX, int NT>
+__device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
+                               typename cplx<Real>::T* out, const unsigned char* rflag,
+                               const FftPass& ps, const typename cplx<Real>::T* tw,
+                               unsigned char* smem) {
+  using T2 = typename cplx<Real>::T;
+  const int tid = threadIdx.x;
+  const int L = ps.L, C = ps.C, csh = ps.cshift;
+  T2* buf = reinterpret_cast<T2*>(smem);
+  T2* twL = buf + L * C;
+  unsigned char* rf = reinterpret_cast<unsigned char*>(twL + L);
+  const int64_t S = ps.S, P = ps.P;
+  const int64_t nsb = (S + C - 1) / C;
+  const int64_t pidx = blk / nsb;
+  const int64_t s0 = (blk - pidx * nsb) * C;
+  const int ceff = (int)((S - s0) < C ? (S - s0) : C);
+  for (int x = tid; x < L; x += NT) {
+    twL[x] = tw[ps.twL_off + x];
+    rf[x] = rflag ? rflag[x] : (unsigned char)1;
+  }
+  __syncthreads();
+  const int E = L * C;
+  const int64_t inbase = pidx * (int64_t)L * S + s0;
+  constexpr int PER = (EMAX + NT - 1) / NT;
+  T2 v[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    v[i] = czero<T2>();
+    if (e < E) {
+      const int l = e >> csh;
+      const int c = e & (C - 1);
+      if (c < ceff && rf[l]) v[i] = in[inbase + (int64_t)l * S + c];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < E) buf[e] = v[i];
+  }
+  __syncthreads();
+  lds_fft<EMAX, NT>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
+  const int64_t mask = ((int64_t)1 << ps.bshift) - 1;
+  const T2* tlo = tw + ps.twlo_off;
+  const T2* thi = tw + ps.twhi_off;
+  const int64_t PS = P * S;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = tid + i * NT;
+    if (e < E) {
+      const int k = e >> csh;
+      const int c = e & (C - 1);
+      if (c < ceff) {
+        const int64_t s = s0 + c;
+        T2 x = buf[e];
+        const int64_t q = s * k;
+        if (q) x = cmul(x, cmul(thi[q >> ps.bshift], tlo[q & mask]));
+        out[(int64_t)k * PS + pidx * S + s] = x;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// A first/middle pass: workgroup = C consecutive columns s of one outer index
+// p; loads L x C elements (C contiguous per row, 128-256 B segments),
+// transforms along L in LDS, applies the inter-pass twiddle and stores with
+// the outer index and k transposed.  Dynamic LDS: L*C elements + L twiddles
+// + L row flags.
+
+// Power of the floating-mean Lomb-Scargle fit from the three normalised sums
+// A = sum w^ y~ e^{iwt}, B = sum w^ e^{iwt}, B2 = sum w^ e^{2iwt}
+// (w^ = w / W).  cos^2 and sin^2 sums follow from B2 by the double-angle
+// identities; the 2x2 fit is solved in closed form (tau-free form).
+__device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, double Bi, double B2r,
+                                           double B2i, const DevStats& st, int norm,
+                                           int fit_mean) {
+  double CC = 0.5 * (1.0 + B2r);
+  double SS = 0.5 * (1.0 - B2r);
+  double CS = 0.5 * B2i;
+  double YC = Ar, YS = Ai;
+  if (fit_mean) {
+    CC -= Br * Br;
+    SS -= Bi * Bi;
+    CS -= Br * Bi;
+    YC -= st.Ybar * Br;
+    YS -= st.Ybar * Bi;
+  }
+  const double D = CC * SS - CS * CS;
+  if (!(D > 0.0)) return 0.0;
+  const double N = SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS;
+  const double YYD = st.YY * D;
+  switch (norm) {
+    case 1:
+      return N / (YYD - N);
+    case 2:
+      return -log1p(-N / YYD);
+    case 3:
+      return 0.5 * st.W * N / D;
+    default:
+      return N / YYD;
+  }
+}
+
+// Last pass: D rows of length L per workgroup for the G grids, transformed in
+// LDS; output k of row p is the mode m = p + P k.  Deconvolution, crop to the
+// nf requested modes and (G = 3) the power are fused into the store.
+// Dynamic LDS: G*D*(L+1) elements + L twiddles.
+// One workgroup's share of the last pass: D rows starting at p0 = blk*D.
+// smem: G*D*(L+1) elements + L twiddles.  nf and K are those of the series
+// (a batched series may use fewer frequencies than its grid's plan).
+template <typename Real, int G, int EMAX, int NT>
+__device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPass& ps,
+                               int64_t n, int64_t nf, int64_t K, const CallArgs& a,
+                               const typename cplx<Real>::T* tw, const double* inv_phihat,
+                               const DevStats& st, unsigned char* smem,
+                               const double* lowfix = nullptr) {
+  using T2 = typename cplx<Real>::T;
+  const int tid = threadIdx.x;
+  const int L = ps.L, D = ps.C;
+  const int Lp = L + 1;
+  T2* buf = reinterpret_cast<T2*>(smem);
+  T2* twL = buf + G * D * Lp;
+  const int64_t P = ps.P;
+  const int64_t p0 = blk * D;
+  const int deff = (int)((P - p0) < D ? (P - p0) : D);
+  for (int x = tid; x < L; x += NT) twL[x] = tw[ps.twL_off + x];
+  const int E = D * L;
+  constexpr int PER = (EMAX / G + NT - 1) / NT;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const T2* in = b.in[g] + p0 * (int64_t)L;
+    T2 v[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      v[i] = czero<T2>();
+      if (e < E && e < deff * L) v[i] = in[e];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + i * NT;
+      if (e < E) {
+        const int d = e / L;
+        const int l = e - d * L;
+        buf[(g * D + d) * Lp + l] = v[i];
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<EMAX, NT>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
+  for (int e = tid; e < E; e += NT) {
+    const int d = e % D;
+    const int k = e / D;
+    if (d >= deff) continue;
+    const int64_t m = p0 + d + P * (int64_t)k;
+    const int64_t mm = (m <= nf - 1 - K) ? m : m - n;
+    const int64_t kout = mm + K;
+    if (kout < 0 || kout >= nf) continue;
+    const double ip = inv_phihat[mm < 0 ? -mm : mm];
+    if (G == 3) {
+      const T2 A = buf[(0 * D + d) * Lp + k];
+      const T2 B = buf[(1 * D + d) * Lp + k];
+      const T2 B2 = buf[(2 * D + d) * Lp + k];
+      double s6[6] = {(double)A.x * ip,  (double)A.y * ip,  (double)B.x * ip,
+                      (double)B.y * ip,  (double)B2.x * ip, (double)B2.y * ip};
+      const int64_t q = kout - st.k_lo;
+      if (lowfix && q >= 0 && q < st.nlow)
+        for (int i = 0; i < 6; ++i) s6[i] = lowfix[6 * q + i];
+      double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean);
+      if (kout == a.kzero) pw = 0.0;
+      a.power[kout] = pw;
+    } else {
+      const T2 A = buf[d * Lp + k];
+      double2 v = make_double2((double)A.x * ip, (double)A.y * ip);
+      reinterpret_cast<double2*>(a.sums)[kout] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Last pass: D rows of length L per workgroup for the G grids, transformed in
+// LDS; output k of row p is the mode m = p + P k.  Deconvolution, crop to the
+// nf requested modes and (G = 3) the power are fused into the store.
+// Dynamic LDS: G*D*(L+1) elements + L twiddles.
+
+// ---------------------------------------------------------------------------
+// Direct sums near f = 0.
+// ---------------------------------------------------------------------------
+// The frequencies k in [k_lo, k_lo + nlow) with |f_k| (tmax - tmin) < 2,
+// at most kLowMax of them, the ones closest to f = 0.
+__device__ __forceinline__ void low_band(const DevStats& st, double f0, double df, int64_t nf,
+                                         int64_t& k_lo, int& nlow) {
+  nlow = 0;
+  k_lo = 0;
+  const double span = st.tmax - st.tmin;
+  if (!(span > 0.0)) return;
+  const double fl = 2.0 / span;
+  double ka = ceil((-fl - f0) / df);
+  double kb = floor((fl - f0) / df);
+  if (ka < 0.0) ka = 0.0;
+  if (kb > (double)(nf - 1)) kb = (double)(nf - 1);
+  if (kb < ka) return;
+  double lo = ka;
+  if (kb - ka + 1.0 > (double)kLowMax) {
+    double centre = rint(-f0 / df);
+    lo = centre - kLowMax / 2;
+    if (lo < ka) lo = ka;
+    if (lo > kb - kLowMax + 1) lo = kb - kLowMax + 1;
+  }
+  k_lo = (int64_t)lo;
+  nlow = (int)fmin(kb - lo + 1.0, (double)kLowMax);
+}
+
+// This thread's contributions to A, B, B2 at frequencies k_lo + g0 + q,
+// q < kLowGroup, summed over points j = j0, j0 + stride, ... < nd.  The phase
+// at the first frequency is reduced in double-double; the others follow by
+// the exact angle-sum recurrence with the step exp(i 2 pi df t).
+__device__ __forceinline__ void low_accumulate(const CallArgs& a, const DevStats& st, int64_t k_first,
+                                               int ng, int64_t j0, int64_t stride,
+                                               double* acc /* 6 * kLowGroup */) {
+#pragma unroll
+  for (int i = 0; i < 6 * kLowGroup; ++i) acc[i] = 0.0;
+  // f_first = f0 + k_first df as a double-double
+  double kp, ke;
+  dd_two_prod((double)k_first, a.df, kp, ke);
+  double fh, fe;
+  dd_two_sum(a.f0, kp, fh, fe);
+  const double fl = fe + ke;
+  const double invW = 1.0 / st.W;
+  for (int64_t j = j0; j < a.nd; j += stride) {
+    const double t = a.t[j];
+    double wj = 1.0;
+    if (a.dy) {
+      const double dv = a.dy[j];
+      wj = 1.0 / (dv * dv);
+    }
+    const double wh = wj * invW;
+    const double wy = wh * (a.y[j] - st.ysub);
+    double pc, ps, sc, ss;
+    prephase(t, st.tau, fh, fl, pc, ps);
+    prephase(t, st.tau, a.df, 0.0, sc, ss);
+#pragma unroll
+    for (int q = 0; q < kLowGroup; ++q) {
+      if (q < ng) {
+        const double c2 = pc * pc - ps * ps, s2 = 2.0 * pc * ps;
+        acc[6 * q + 0] += wy * pc;
+        acc[6 * q + 1] += wy * ps;
+        acc[6 * q + 2] += wh * pc;
+        acc[6 * q + 3] += wh * ps;
+        acc[6 * q + 4] += wh * c2;
+        acc[6 * q + 5] += wh * s2;
+      }
+      const double nc = pc * sc - ps * ss;
+      ps = pc * ss + ps * sc;
+      pc = nc;
+    }
+  }
+}
+
+// Sum `cnt` doubles of every thread of the workgroup; thread i < cnt gets the
+// total of value i.  red: LDS of (NT / 64) * cnt doubles.
+template <int NT, int CNT>
+__device__ __forceinline__ void block_sum(const double* v, double* red, double* out) {
+  constexpr int cnt = CNT;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < cnt; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave * cnt + i] = x;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[w * cnt + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+}  // namespace mils

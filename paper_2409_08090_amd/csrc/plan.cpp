@@ -153,10 +153,13 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   nmin = std::max<int64_t>(nmin, 16);
   const int G = r.G;
   const int emid = r.prec == 1 ? kEmid32 : kEmid64;
-  const int elast = r.prec == 1 ? kElast32 : kElast64;
+  const int elast = r.batch ? (r.prec == 1 ? kElastBatch32 : kElastBatch64)
+                            : (r.prec == 1 ? kElast32 : kElast64);
+  const int dmin = r.batch ? 1 : 4;
   const int cmax = 32;
 
-  auto cand = smooth_in_range(nmin, 2 * nmin + 64);
+  std::vector<int64_t> cand = r.n_fixed > 0 ? std::vector<int64_t>{r.n_fixed}
+                                             : smooth_in_range(nmin, 2 * nmin + 64);
   double best_cost = 1e300;
   int best_np = 0;
   int64_t best_n = 0;
@@ -173,8 +176,8 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
           ok = true;
         }
       } else {
-        // last length: largest with >= 4 rows per workgroup
-        const int llast_max = std::min<int64_t>(elast / (G * 4) - 1, kLmaxPass);
+        // last length: largest with >= dmin rows per workgroup
+        const int llast_max = std::min<int64_t>(elast / (G * dmin) - 1, kLmaxPass);
         for (int Ll = llast_max; Ll >= 2 && !ok; --Ll) {
           if (n % Ll || !is_smooth(Ll)) continue;
           std::vector<int> mids;
@@ -226,6 +229,10 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     } else {
       int d = 1;
       while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P) d *= 2;
+      if (G * d * (ps.L + 1) > elast) {
+        if (err) *err = "last FFT pass does not fit one workgroup";
+        return false;
+      }
       ps.C = d;
       p.D = d;
     }
@@ -341,6 +348,8 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
   } else {
     x.hs = reinterpret_cast<double*>(take(sizeof(double) * nd));
   }
+  x.lowpart = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowBlocks));
+  x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax));
   x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));
   const size_t cbytes = p.prec == 1 ? 8 : 16;

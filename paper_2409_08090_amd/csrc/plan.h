@@ -18,6 +18,8 @@ struct PlanRequest {
   int prec;             // 0 FP64, 1 FP32
   int G;                // grids transformed together in the last pass (3 or 1)
   double sigma = 0.0;   // upsampling factor; 0 = the precision's default
+  bool batch = false;   // plan for the persistent batched kernel (256-thread last pass)
+  int64_t n_fixed = 0;  // use exactly this grid size (must factor), 0 = choose
 };
 
 // Default upsampling factor of a precision.

@@ -281,3 +281,28 @@ def periodogram_batch(t, y, dy, nd_off, nf_off, f0, df, eps=1e-9, precision="fp6
     if rc not in (MILS_OK, MILS_ERR_INVALID_ARG, MILS_ERR_DEGENERATE) or not return_status:
         ctx.check(rc)
     return (out, st) if return_status else out
+
+
+def pack_curves(curves, device=None, with_dy=True):
+    """CSR packing of a list of workloads.Curve for periodogram_batch:
+    returns (t, y, dy, nd_off, nf_off, f0, df) with device tensors for the data."""
+    import numpy as np
+    import torch
+    nd = np.array([c.t.size for c in curves], dtype=np.int64)
+    nf = np.array([c.nf for c in curves], dtype=np.int64)
+    nd_off = np.concatenate([[0], np.cumsum(nd)]).astype(np.int64)
+    nf_off = np.concatenate([[0], np.cumsum(nf)]).astype(np.int64)
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    cat = lambda xs: torch.from_numpy(np.ascontiguousarray(np.concatenate(xs), dtype=np.float64)).to(dev)  # noqa: E731
+    t = cat([c.t for c in curves])
+    y = cat([c.y for c in curves])
+    dy = cat([c.dy for c in curves]) if with_dy else None
+    f0 = np.array([c.f0 for c in curves], dtype=np.float64)
+    df = np.array([c.df for c in curves], dtype=np.float64)
+    return t, y, dy, nd_off, nf_off, f0, df
+
+
+def split_power(power, nf_off):
+    """Per-series numpy views of a batched power tensor."""
+    p = power.cpu().numpy()
+    return [p[nf_off[i]:nf_off[i + 1]] for i in range(len(nf_off) - 1)]
