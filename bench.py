@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -197,6 +199,48 @@ def main():
             bms = (time.perf_counter() - b0) * 1e3 / nb
             extra["batch"][prec] = {"ms_per_batch": round(bms, 3),
                                     "value": bsums / (bms * 1e-3), "eps": e}
+
+    # serving: open-loop Poisson arrivals at 2000 requests/s of mixed sizes and
+    # precisions (a pool of 192 synthetic curves with N_d log-uniform in
+    # [50, 2e5], reused by the arrivals), continuous batching on 3 lanes
+    if not args.no_serve:
+        rng = np.random.default_rng(4)
+        pool = []
+        for _ in range(192):
+            ndq = int(np.floor(np.exp(rng.uniform(np.log(50), np.log(200_000)))))
+            pool.append(workloads.batch_curve(rng, ndq))
+        srv = mils.Server(0, lanes=3)
+        rate, dur = 2000.0, args.serve_seconds
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, int(rate * dur * 1.2)))
+        arrivals = arrivals[arrivals < dur]
+        picks = rng.integers(0, len(pool), arrivals.size)
+        precs = rng.random(arrivals.size) < 0.5
+        tickets = []
+        busy = 0
+        s0 = time.perf_counter()
+        for a_t, pi, use32 in zip(arrivals, picks, precs):
+            while time.perf_counter() - s0 < a_t:
+                pass
+            cq = pool[pi]
+            prec, e = ("fp32", 1e-5) if use32 else ("fp64", 1e-9)
+            rc, tk = srv.submit(cq.t, cq.y, cq.dy, cq.f0, cq.df, cq.nf, eps=e, precision=prec)
+            if rc == mils.MILS_OK:
+                tickets.append((tk, cq.nf))
+            else:
+                busy += 1
+        for tk, nfq in tickets:
+            srv.wait(tk)
+            srv.take(tk, nfq)
+        ss = srv.stats()
+        srv.close()
+        extra["serving"] = {"rate_req_s": rate, "seconds": dur, "offered": int(arrivals.size),
+                            "completed": ss["completed"], "rejected": busy + ss["rejected"],
+                            "p50_ms": round(ss["latency_p50_ms"], 3),
+                            "p99_ms": round(ss["latency_p99_ms"], 3),
+                            "max_ms": round(ss["latency_max_ms"], 3),
+                            "sustained_sums_per_s": ss["sums_per_s"],
+                            "mean_batch": round(ss["mean_batch"], 2), "batches": ss["batches"],
+                            "peak_inflight_bytes": ss["peak_inflight_bytes"]}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -179,6 +179,70 @@ int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd
                            int32_t *status_per_curve, void *hip_stream);
 
 /*
+ * Serving loop: requests of mixed sizes and precisions are submitted from host
+ * memory, admitted while the device memory they need fits the HBM budget,
+ * packed as they arrive into batches that run concurrently on `lanes`
+ * streams (a lane that frees up takes everything that has arrived: continuous
+ * batching), and read back to host memory.  Requests whose frequency count
+ * exceeds the batch limit run through the single-series path on a lane.
+ * Thread-safe: any host thread may submit, poll, wait and take.
+ */
+typedef struct mils_server mils_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device bytes for requests in flight (0 = 8 GiB) */
+  int32_t lanes;             /* concurrent batches / streams (0 = 2) */
+  int32_t max_batch;         /* requests per batch (0 = 4096) */
+  int32_t queue_capacity;    /* pending requests before submit returns MILS_ERR_BUSY (0 = 65536) */
+  int32_t tick_us;           /* how long an idle lane waits for more arrivals (0 = 200) */
+} mils_server_config;
+
+typedef struct {
+  const double *t;    /* host, nd values; copied by submit */
+  const double *y;    /* host, nd values; copied by submit */
+  const double *dy;   /* host, nd values or NULL; copied by submit */
+  int64_t nd;
+  mils_params params; /* grid, tolerance, precision, normalisation, flags */
+} mils_request;
+
+enum { MILS_REQ_PENDING = 0, MILS_REQ_RUNNING = 1, MILS_REQ_DONE = 2 };
+
+typedef struct {
+  double submit_s;    /* seconds since the server started */
+  double start_s;     /* when its batch was launched */
+  double done_s;      /* when its result reached host memory */
+  int32_t status;     /* MILS_OK or the request's error */
+  int32_t batch_size; /* requests in its batch */
+} mils_request_stats;
+
+typedef struct {
+  uint64_t submitted, completed, rejected, batches;
+  uint64_t inflight_bytes, peak_inflight_bytes;
+  double latency_p50_ms, latency_p99_ms, latency_max_ms; /* submit -> result on host */
+  double sums_per_s;  /* sum of nd*nf over completed requests / (last done - first submit) */
+  double mean_batch;  /* requests per batch */
+} mils_server_counters;
+
+/* Create a server on HIP device `device` (cfg may be NULL for defaults). */
+int mils_server_create(int device, const mils_server_config *cfg, mils_server **out);
+/* Copy the request's arrays and queue it; *ticket identifies it.  Returns
+ * MILS_ERR_BUSY when the queue is full, MILS_ERR_OOM when the request alone
+ * exceeds the budget, MILS_ERR_INVALID_ARG for bad arguments. */
+int mils_server_submit(mils_server *srv, const mils_request *req, uint64_t *ticket);
+/* *state = MILS_REQ_PENDING / RUNNING / DONE. */
+int mils_server_poll(mils_server *srv, uint64_t ticket, int32_t *state);
+/* Wait until the request is done (timeout_us < 0: forever); MILS_ERR_TIMEOUT otherwise. */
+int mils_server_wait(mils_server *srv, uint64_t ticket, int64_t timeout_us);
+/* Copy a done request's power (params.nf doubles, host) and statistics (st
+ * may be NULL; power may be NULL to discard), release the ticket, and return
+ * the request's status. */
+int mils_server_take(mils_server *srv, uint64_t ticket, double *power, mils_request_stats *st);
+int mils_server_stats(mils_server *srv, mils_server_counters *out);
+/* Stop the lanes; requests not yet done are cancelled (their tickets become
+ * invalid).  Waits for batches already on the device. */
+int mils_server_destroy(mils_server *srv);
+
+/*
  * Per-stage timing of the single-series path (measurement support).  While
  * enabled, every call records a pair of HIP events around each stage of the
  * path on the call's stream.  Stages: 0 statistics, 1 binning / sort,

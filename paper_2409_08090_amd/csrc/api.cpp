@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/mils.h"
+#include "api_internal.h"
 #include "batch.h"
 #include "kernels.h"
 #include "mils_internal.h"
@@ -464,11 +465,19 @@ int mils_periodogram(mils_context* ctx, const double* t, const double* y, const 
                     reinterpret_cast<hipStream_t>(hip_stream), true);
 }
 
-int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off,
-                           const double* t, const double* y, const double* dy,
-                           const int64_t* nf_off, const double* f0, const double* df,
-                           const mils_params* common, double* power, int32_t* status_per_curve,
-                           void* hip_stream) {
+}  // extern "C"
+
+int mils_check_params(const mils_params* p, int64_t nd) {
+  int rc = check_nd(nd);
+  return rc != MILS_OK ? rc : check_params(p);
+}
+
+// Body of mils_periodogram_batch; the serving loop calls it with
+// use_graph = false (its batches change with every call).
+int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, const double* t,
+                   const double* y, const double* dy, const int64_t* nf_off, const double* f0,
+                   const double* df, const mils_params* common, double* power,
+                   int32_t* status_per_curve, void* hip_stream, bool use_graph) {
   if (!ctx) return MILS_ERR_INVALID_ARG;
   if (ncurves < 1 || ncurves > (int64_t)0x7fffffff || !nd_off || !nf_off || !f0 || !df ||
       !common || !t || !y || !power)
@@ -660,24 +669,10 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
     layout_work(big, nd_max, 3, B.ws, &ba.w0);
     ba.slot_stride = slot_bytes;
     B.status_dev = ba.status;
-    // slot statistics blocks hold no counters, nothing to clear
-    // capture the launch (queue reset + persistent kernel) as a graph
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
     if (B.graph) (void)hipGraphDestroy(B.graph);
     B.exec = nullptr;
     B.graph = nullptr;
-    if (!B.cap_stream) {
-      he = hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking);
-      if (he != hipSuccess) return hip_fail(ctx, he, "capture stream");
-    }
-    he = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
-      hipError_t le = launch_batch(ba, nslots, prec, B.cap_stream);
-      he = hipStreamEndCapture(B.cap_stream, &B.graph);
-      if (le != hipSuccess) he = le;
-    }
-    if (he == hipSuccess) he = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
-    if (he != hipSuccess) return hip_fail(ctx, he, "batch graph capture");
     B.args = ba;
     B.nslots = nslots;
     B.prec = prec;
@@ -685,7 +680,22 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
     B.key = key;
     B.valid = true;
   }
-  he = hipGraphLaunch(B.exec, stream);
+  if (use_graph && !B.exec) {
+    // capture the launch (queue reset + persistent kernel) once per batch layout
+    if (!B.cap_stream) {
+      he = hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking);
+      if (he != hipSuccess) return hip_fail(ctx, he, "capture stream");
+    }
+    he = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      hipError_t le = launch_batch(B.args, B.nslots, B.prec, B.cap_stream);
+      he = hipStreamEndCapture(B.cap_stream, &B.graph);
+      if (le != hipSuccess) he = le;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) return hip_fail(ctx, he, "batch graph capture");
+  }
+  he = use_graph ? hipGraphLaunch(B.exec, stream) : launch_batch(B.args, B.nslots, B.prec, stream);
   if (he == hipSuccess)
     he = hipMemcpyAsync(B.status_host, B.status_dev, sizeof(int32_t) * ncurves,
                         hipMemcpyDeviceToHost, stream);
@@ -700,6 +710,17 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
   }
   if (worst != MILS_OK) ctx->err = "some series of the batch have invalid or constant data";
   return worst;
+}
+
+extern "C" {
+
+int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off,
+                           const double* t, const double* y, const double* dy,
+                           const int64_t* nf_off, const double* f0, const double* df,
+                           const mils_params* common, double* power, int32_t* status_per_curve,
+                           void* hip_stream) {
+  return mils_batch_run(ctx, ncurves, nd_off, t, y, dy, nf_off, f0, df, common, power,
+                        status_per_curve, hip_stream, true);
 }
 
 int mils_profile_enable(mils_context* ctx, int enable) {

@@ -210,19 +210,30 @@ __device__ __forceinline__ void block_fence() {
 
 // Phase wrappers kept out of line: each phase gets its own register
 // allocation instead of the union of all of them.
+// A batched series spreads tiles of several whole rows, up to what the
+// dynamic LDS holds for geometry f (two grids), to amortise the per-tile cost.
 template <typename Real>
-__device__ __noinline__ void batch_spread_f(int tile, const CallArgs& a, const Plan& p,
-                                            const Work& w, const DevStats& st,
-                                            unsigned char* smem, int* rb, int* re, int* sv) {
-  spread_tile<Real, 1, 2, NT>(tile, a, p, w, st, 0, w.rowflag_f, reinterpret_cast<Real*>(smem),
-                              rb, re, sv);
+__device__ __forceinline__ int batch_tile_cells() {
+  return kBatchLds / (2 * 2 * (int)sizeof(Real));
 }
 template <typename Real>
-__device__ __noinline__ void batch_spread_2f(int tile, const CallArgs& a, const Plan& p,
+__device__ __forceinline__ int batch_tile(const Plan& p) {
+  const int cap = batch_tile_cells<Real>();
+  return p.S1 <= cap ? (int)(p.S1 * (cap / p.S1)) : p.T;
+}
+template <typename Real>
+__device__ __noinline__ void batch_spread_f(int tile, int Tt, const CallArgs& a, const Plan& p,
+                                            const Work& w, const DevStats& st,
+                                            unsigned char* smem, int* rb, int* re, int* sv) {
+  spread_tile<Real, 1, 2, NT>(tile, Tt, batch_tile_cells<Real>(), a, p, w, st, 0, w.rowflag_f,
+                              reinterpret_cast<Real*>(smem), rb, re, sv);
+}
+template <typename Real>
+__device__ __noinline__ void batch_spread_2f(int tile, int Tt, const CallArgs& a, const Plan& p,
                                              const Work& w, const DevStats& st,
                                              unsigned char* smem, int* rb, int* re, int* sv) {
-  spread_tile<Real, 2, 1, NT>(tile, a, p, w, st, 2, w.rowflag_2f, reinterpret_cast<Real*>(smem),
-                              rb, re, sv);
+  spread_tile<Real, 2, 1, NT>(tile, Tt, batch_tile_cells<Real>(), a, p, w, st, 2, w.rowflag_2f,
+                              reinterpret_cast<Real*>(smem), rb, re, sv);
 }
 template <typename Real>
 __device__ __forceinline__ void batch_pass(int64_t blk, const typename cplx<Real>::T* in,
@@ -337,9 +348,12 @@ __global__ __launch_bounds__(NT, 2) void k_batch(BatchArgs ba) {
     const T2* tw = reinterpret_cast<const T2*>(ba.tw[sc.plan]);
     const double* iph = ba.inv_phihat[sc.plan];
     // spreads
-    const int ntiles = (int)((p.S1 / p.T) * p.nrows);
-    for (int tile = 0; tile < ntiles; ++tile) batch_spread_f<Real>(tile, a, p, w, sts, smem, rb, re, sv);
-    for (int tile = 0; tile < ntiles; ++tile) batch_spread_2f<Real>(tile, a, p, w, sts, smem, rb, re, sv);
+    const int Tt = batch_tile<Real>(p);
+    const int ntiles = (int)((p.n + Tt - 1) / Tt);
+    for (int tile = 0; tile < ntiles; ++tile)
+      batch_spread_f<Real>(tile, Tt, a, p, w, sts, smem, rb, re, sv);
+    for (int tile = 0; tile < ntiles; ++tile)
+      batch_spread_2f<Real>(tile, Tt, a, p, w, sts, smem, rb, re, sv);
     block_fence();
     // FFT passes: pass 0 in place on grid, then grid -> grid2 -> grid ...
     const int npass = p.npass;

@@ -308,7 +308,8 @@ __global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w,
   if (stp->status != 0) return;
   const int ntiles = (int)((p.S1 / p.T) * p.nrows);
   const int tile = (int)xcd_remap(blockIdx.x, ntiles);
-  spread_tile<Real, GEO, NG, kThreads>(tile, a, p, w, *stp, gbase, rowflag, acc, rb, re, sv);
+  spread_tile<Real, GEO, NG, kThreads>(tile, p.T, kTileMax, a, p, w, *stp, gbase, rowflag, acc, rb,
+                                       re, sv);
 }
 
 // ============================================================================
@@ -370,11 +371,18 @@ __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
   __syncthreads();
   if (!amLast) return;
   __threadfence();
-  for (int i = threadIdx.x; i < 6 * nlow; i += kThreads) {
-    double s = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b)
-      s += ((volatile double*)w.lowpart)[(size_t)b * 6 * kLowMax + i];
-    w.lowfix[i] = s;
+  // thread b holds partial b (gridDim.x <= kThreads); one block-wide sum per value
+  double v[6 * kLowMax];
+  const bool have = threadIdx.x < gridDim.x;
+#pragma unroll
+  for (int i = 0; i < 6 * kLowMax; ++i)
+    v[i] = (have && i < 6 * nlow) ? w.lowpart[(size_t)threadIdx.x * 6 * kLowMax + i] : 0.0;
+  __shared__ double red2[(kThreads / 64) * 6 * kLowGroup];
+#pragma unroll
+  for (int g0 = 0; g0 < kLowMax; g0 += kLowGroup) {
+    block_sum<kThreads, 6 * kLowGroup>(v + 6 * g0, red2, tot);
+    if ((int)threadIdx.x < 6 * kLowGroup && 6 * g0 + (int)threadIdx.x < 6 * nlow)
+      w.lowfix[6 * g0 + threadIdx.x] = tot[threadIdx.x];
   }
   if (threadIdx.x == 0) {
     stp->k_lo = k_lo;
@@ -430,6 +438,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
   if (a.periodogram)
     hipLaunchKernelGGL(k_lowfreq, dim3(grid_for(a.nd, kLowBlocks)), dim3(kThreads), 0, s, a, w);
+  static_assert(kLowBlocks <= kThreads, "one partial per thread in the final sum");
   mark(kStageStats, 0);
   mark(kStageBin, 1);
   const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);

@@ -88,32 +88,36 @@ __device__ __forceinline__ int gather_ranges(int* rb, int* re, int64_t c0, int64
   return cnt;
 }
 
-// Spread one tile (T cells starting at tile*T of the [nrows][S1] view) of
-// geometry GEO into NG grids.  acc: LDS accumulator of NG*2*kTileMax Reals;
-// rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by every thread of the
-// workgroup (it contains barriers).
+// Spread one tile of geometry GEO into NG grids: cells [tile*T, tile*T + T)
+// of the flat grid, where T either divides the row length S1 of the
+// [nrows][S1] view or is a whole number of rows.  The flag of every row that
+// starts inside the tile is written.  acc: LDS accumulator of NG*2*tcap Reals
+// (T <= tcap); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by every
+// thread of the workgroup (it contains barriers).
 template <typename Real, int GEO, int NG, int NT>
-__device__ void spread_tile(int tile, const CallArgs& a, const Plan& p, const Work& w,
-                            const DevStats& st, int gbase, unsigned char* rowflag, Real* acc,
-                            int* rb, int* re, int* sv) {
+__device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const Plan& p,
+                            const Work& w, const DevStats& st, int gbase, unsigned char* rowflag,
+                            Real* acc, int* rb, int* re, int* sv) {
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
-  const int tiles_per_row = (int)(p.S1 / p.T);
-  const int row = tile / tiles_per_row;
-  const int seg = tile - row * tiles_per_row;
-  const int64_t a0 = (int64_t)row * p.S1 + (int64_t)seg * p.T;
+  const int64_t a0 = (int64_t)tile * Tt;
+  const int T = (int)((p.n - a0) < Tt ? (p.n - a0) : Tt);
   const int h = (int)ceil(p.hw) + 1;
   const int nd = (int)a.nd;
   const int* bs = w.bin_start;
   if (tid == 0) {
-    int cnt = gather_ranges<GEO>(rb, re, (int64_t)row * p.S1 - h, (int64_t)(row + 1) * p.S1 + h,
-                                 p, bs, nd);
-    int tot = 0;
-    for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
-    const int active = tot > 0;
-    if (seg == 0) rowflag[row] = (unsigned char)active;
-    sv[1] = active;
-    sv[0] = active ? gather_ranges<GEO>(rb, re, a0 - h, a0 + p.T + h, p, bs, nd) : 0;
+    const int64_t r0 = a0 / p.S1, r1 = (a0 + T - 1) / p.S1;
+    int any = 0;
+    for (int64_t r = r0; r <= r1; ++r) {
+      int cnt = gather_ranges<GEO>(rb, re, r * p.S1 - h, (r + 1) * p.S1 + h, p, bs, nd);
+      int tot = 0;
+      for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
+      const int active = tot > 0;
+      if (r * p.S1 >= a0) rowflag[r] = (unsigned char)active;
+      any |= active;
+    }
+    sv[1] = any;
+    sv[0] = any ? gather_ranges<GEO>(rb, re, a0 - h, a0 + T + h, p, bs, nd) : 0;
   }
   __syncthreads();
   const int active = sv[1];
@@ -122,12 +126,11 @@ __device__ void spread_tile(int tile, const CallArgs& a, const Plan& p, const Wo
     __syncthreads();  // sv/rb/re are reused by the next tile
     return;
   }
-  const int T = p.T;
   for (int x = tid; x < T; x += NT) {
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-      acc[(2 * g) * kTileMax + x] = 0;
-      acc[(2 * g + 1) * kTileMax + x] = 0;
+      acc[(2 * g) * tcap + x] = 0;
+      acc[(2 * g + 1) * tcap + x] = 0;
     }
   }
   __syncthreads();
@@ -200,8 +203,8 @@ __device__ void spread_tile(int tile, const CallArgs& a, const Plan& p, const Wo
         const Real v = es_kernel(z, beta);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          atomicAdd(&acc[(2 * g) * kTileMax + loc], v * hre[g]);
-          atomicAdd(&acc[(2 * g + 1) * kTileMax + loc], v * him[g]);
+          atomicAdd(&acc[(2 * g) * tcap + loc], v * hre[g]);
+          atomicAdd(&acc[(2 * g + 1) * tcap + loc], v * him[g]);
         }
       }
     }
@@ -212,8 +215,8 @@ __device__ void spread_tile(int tile, const CallArgs& a, const Plan& p, const Wo
     T2* out = reinterpret_cast<T2*>(w.grid[gbase + g]);
     for (int x = tid; x < T; x += NT) {
       T2 v;
-      v.x = acc[(2 * g) * kTileMax + x];
-      v.y = acc[(2 * g + 1) * kTileMax + x];
+      v.x = acc[(2 * g) * tcap + x];
+      v.y = acc[(2 * g + 1) * tcap + x];
       out[a0 + x] = v;
     }
   }

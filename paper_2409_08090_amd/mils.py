@@ -43,6 +43,32 @@ class mils_plan_desc(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_uint64)]
 
 
+class mils_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("lanes", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("tick_us", ctypes.c_int32)]
+
+
+class mils_request(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p), ("y", ctypes.c_void_p), ("dy", ctypes.c_void_p),
+                ("nd", ctypes.c_int64), ("params", mils_params)]
+
+
+class mils_request_stats(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("status", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32)]
+
+
+class mils_server_counters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("inflight_bytes", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64),
+                ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double), ("sums_per_s", ctypes.c_double),
+                ("mean_batch", ctypes.c_double)]
+
+
 class MilsError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"libmils error {status}: {message}")
@@ -79,6 +105,16 @@ SIGNATURES = {
     "mils_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "mils_profile_stage_name": ([ctypes.c_int], ctypes.c_char_p),
     "mils_profile_read": ([_P, _D, _I64P], ctypes.c_int),
+    "mils_server_create": ([ctypes.c_int, ctypes.POINTER(mils_server_config), ctypes.POINTER(_P)],
+                           ctypes.c_int),
+    "mils_server_submit": ([_P, ctypes.POINTER(mils_request), ctypes.POINTER(ctypes.c_uint64)],
+                           ctypes.c_int),
+    "mils_server_poll": ([_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "mils_server_wait": ([_P, ctypes.c_uint64, ctypes.c_int64], ctypes.c_int),
+    "mils_server_take": ([_P, ctypes.c_uint64, _P, ctypes.POINTER(mils_request_stats)],
+                         ctypes.c_int),
+    "mils_server_stats": ([_P, ctypes.POINTER(mils_server_counters)], ctypes.c_int),
+    "mils_server_destroy": ([_P], ctypes.c_int),
 }
 
 MILS_NUM_STAGES = 8
@@ -306,3 +342,72 @@ def split_power(power, nf_off):
     """Per-series numpy views of a batched power tensor."""
     p = power.cpu().numpy()
     return [p[nf_off[i]:nf_off[i + 1]] for i in range(len(nf_off) - 1)]
+
+
+class Server:
+    """Serving loop on one device (mils_server_*): submit host arrays, get
+    tickets, wait and take host results."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, lanes=0, max_batch=0, queue_capacity=0,
+                 tick_us=0):
+        lib = load()
+        cfg = mils_server_config(int(hbm_budget_bytes), int(lanes), int(max_batch),
+                                 int(queue_capacity), int(tick_us))
+        h = _P()
+        rc = lib.mils_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
+        if rc != MILS_OK:
+            raise MilsError(rc, "mils_server_create failed")
+        self.handle = h
+
+    def submit(self, t, y, dy, f0, df, nf, eps=1e-9, precision="fp64",
+               normalization="standard", center_data=True, fit_mean=True):
+        """Returns (status, ticket); status is MILS_OK, MILS_ERR_BUSY, ..."""
+        import numpy as np
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        dyp = None
+        if dy is not None:
+            dy = np.ascontiguousarray(dy, dtype=np.float64)
+            dyp = dy.ctypes.data
+        req = mils_request(t.ctypes.data, y.ctypes.data, dyp, t.size,
+                           make_params(f0, df, nf, eps, precision, normalization, center_data,
+                                       fit_mean))
+        tk = ctypes.c_uint64()
+        rc = load().mils_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk))
+        return rc, tk.value
+
+    def poll(self, ticket):
+        st = ctypes.c_int32()
+        rc = load().mils_server_poll(self.handle, ticket, ctypes.byref(st))
+        return rc, st.value
+
+    def wait(self, ticket, timeout_us=-1):
+        return load().mils_server_wait(self.handle, ticket, int(timeout_us))
+
+    def take(self, ticket, nf):
+        """(status, power numpy array or None, stats dict)."""
+        import numpy as np
+        out = np.empty(int(nf))
+        st = mils_request_stats()
+        rc = load().mils_server_take(self.handle, ticket, out.ctypes.data, ctypes.byref(st))
+        stats = {"submit_s": st.submit_s, "start_s": st.start_s, "done_s": st.done_s,
+                 "status": st.status, "batch_size": st.batch_size}
+        return rc, (out if rc == MILS_OK else None), stats
+
+    def stats(self) -> dict:
+        c = mils_server_counters()
+        rc = load().mils_server_stats(self.handle, ctypes.byref(c))
+        if rc != MILS_OK:
+            raise MilsError(rc, "mils_server_stats failed")
+        return {f: getattr(c, f) for f, _ in mils_server_counters._fields_}
+
+    def close(self):
+        if self.handle:
+            load().mils_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

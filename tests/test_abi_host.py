@@ -119,9 +119,10 @@ def test_planner_invariants(nf, eps, prec):
     assert _smooth(n)
     assert math.prod(d["len"]) == n
     assert 1 <= d["npass"] <= 4
-    assert 2 <= d["width"] <= 16
+    assert 2 <= d["width"] <= 20
     # the ES aliasing estimate exp(-pi w sqrt(1 - 1/sigma)) meets the tolerance
-    assert math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])) <= eps / 2 * 1.0001
+    margin = 8 if prec == "fp64" else 2
+    assert math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])) <= eps / margin * 1.0001
     assert n % d["tile"] == 0 and d["tile"] <= 1024
 
 
@@ -138,4 +139,15 @@ def test_kernel_error_estimate_falls_with_tolerance():
 
 def test_cfg1_shape_uses_three_lds_passes():
     d = mils.plan_info(nd=1_000_000, nf=12_000_000, eps=1e-9)
-    assert d["npass"] == 3 and d["n"] >= 15_000_000 and d["width"] == 16
+    assert d["npass"] == 3 and d["n"] >= 15_000_000 and d["width"] == 17
+
+
+def test_server_config_and_device_checks():
+    lib = mils.load()
+    h = ctypes.c_void_p()
+    bad = mils.mils_server_config(0, 99, 0, 0, 0)
+    assert lib.mils_server_create(0, ctypes.byref(bad), ctypes.byref(h)) == mils.MILS_ERR_INVALID_ARG
+    assert lib.mils_server_create(-1, None, ctypes.byref(h)) == mils.MILS_ERR_DEVICE
+    assert lib.mils_server_create(0, None, None) == mils.MILS_ERR_INVALID_ARG
+    assert lib.mils_server_submit(None, None, None) == mils.MILS_ERR_INVALID_ARG
+    assert lib.mils_server_destroy(None) == mils.MILS_ERR_INVALID_ARG
