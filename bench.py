@@ -15,7 +15,6 @@ baseline.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -40,21 +39,12 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one device copy of 2^30 bytes (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     return ap.parse_args()
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2409_08090_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, fn), "rb") as f:
-                h.update(fn.encode())
-                h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def active_fraction(t, df, geo, plan, tau):
@@ -103,7 +93,7 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_2409_08090_amd import mils, workloads
+    from paper_2409_08090_amd import mils, traffic as trafficmod, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -152,7 +142,8 @@ def main():
     if os.path.exists(tpath):
         try:
             rec = json.load(open(tpath))
-            if rec.get("kernel_hash") == kernel_source_hash() and dom in rec.get("bytes", {}):
+            if rec.get("kernel_hash") == trafficmod.kernel_source_hash(ROOT) and \
+                    dom in rec.get("bytes", {}):
                 traffic = rec["bytes"][dom]
         except Exception:
             traffic = None
@@ -162,6 +153,13 @@ def main():
     whole_path_bytes = sum(bytes_model[k] for k in prof)
     extra = {"stages": stages, "active_rows": {"f": round(rf, 4), "2f": round(r2, 4)},
              "plan": plan, "whole_path_alg_GBs": round(whole_path_bytes / (ms_per_step * 1e-3) / 1e9, 1)}
+
+    if args.calibrate_copy:
+        src = torch.empty(trafficmod.COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # FP32 precision form on the same curve
     if not args.no_extra:

@@ -153,32 +153,34 @@ __global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
 // Binning.  bin_start[b] = index of the first point (in the order the spread
 // reads them) whose cell lies in bin b or later; bin_start[nbins] = nd.
 // ============================================================================
-// Sorted fast path: the bins of consecutive points are non-decreasing, so the
-// bin starts are the positions where the bin index steps up.  A descent sets
-// need_sort and the counting sort below rebuilds everything.
+// Sorted fast path: when the bins of consecutive points are non-decreasing,
+// bin_start[b] is the first point whose bin is >= b, found by a binary search
+// per bin (every bin costs the same, whatever the gaps in the data).  Each
+// point also checks its predecessor; a descent sets need_sort and the
+// counting sort below rebuilds everything.
 __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Work w) {
   const DevStats* st = w.stats;
   if (st->status != 0 || st->need_sort) return;
   const double tau = st->tau;
-  const int64_t nd = a.nd;
-  const int64_t nb = p.nbins;
-  const int kfirst = point_bin(a.t[0], tau, a.df, p);
-  const int klast = point_bin(a.t[nd - 1], tau, a.df, p);
+  const int nd = (int)a.nd;
+  const int nb = (int)p.nbins;
   const int64_t total = nd > nb + 1 ? nd : nb + 1;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kThreads) {
-    if (i <= nb) {
-      if (i <= kfirst) w.bin_start[i] = 0;
-      else if (i > klast) w.bin_start[i] = (int)nd;
-    }
     if (i >= 1 && i < nd) {
       const int kp = point_bin(a.t[i - 1], tau, a.df, p);
       const int kc = point_bin(a.t[i], tau, a.df, p);
-      if (kc < kp) {
-        atomicOr(&w.stats->need_sort, 1);
-      } else {
-        for (int b = kp + 1; b <= kc; ++b) w.bin_start[b] = (int)i;
+      if (kc < kp) atomicOr(&w.stats->need_sort, 1);
+    }
+    if (i <= nb) {
+      const int b = (int)i;
+      int lo = 0, hi = nd;  // first j in [0, nd) with bin(j) >= b, else nd
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (point_bin(a.t[mid], tau, a.df, p) < b) lo = mid + 1;
+        else hi = mid;
       }
+      w.bin_start[b] = lo;
     }
   }
 }
@@ -306,8 +308,9 @@ __global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w,
   __shared__ int rb[8], re[8], sv[2];
   const DevStats* stp = w.stats;
   if (stp->status != 0) return;
-  const int ntiles = (int)((p.S1 / p.T) * p.nrows);
-  const int tile = (int)xcd_remap(blockIdx.x, ntiles);
+  // tiles in launch order: consecutive tiles land on different XCDs, which
+  // spreads the active rows (a contiguous fraction of the grid) over the chip
+  const int tile = blockIdx.x;
   spread_tile<Real, GEO, NG, kThreads>(tile, p.T, kTileMax, a, p, w, *stp, gbase, rowflag, acc, rb,
                                        re, sv);
 }

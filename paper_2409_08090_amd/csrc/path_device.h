@@ -388,16 +388,37 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
     }
   }
   __syncthreads();
-  lds_fft<EMAX, NT>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
-  for (int e = tid; e < E; e += NT) {
+  // kernel-transform factors of this thread's outputs, fetched before the
+  // transform so that their latency overlaps it (-1: output cropped)
+  constexpr int PO = (EMAX / G + NT - 1) / NT;
+  double ipv[PO];
+  int64_t kov[PO];
+#pragma unroll
+  for (int i = 0; i < PO; ++i) {
+    const int e = tid + i * NT;
     const int d = e % D;
     const int k = e / D;
-    if (d >= deff) continue;
-    const int64_t m = p0 + d + P * (int64_t)k;
-    const int64_t mm = (m <= nf - 1 - K) ? m : m - n;
-    const int64_t kout = mm + K;
-    if (kout < 0 || kout >= nf) continue;
-    const double ip = inv_phihat[mm < 0 ? -mm : mm];
+    kov[i] = -1;
+    ipv[i] = 0.0;
+    if (e < E && d < deff) {
+      const int64_t m = p0 + d + P * (int64_t)k;
+      const int64_t mm = (m <= nf - 1 - K) ? m : m - n;
+      const int64_t kout = mm + K;
+      if (kout >= 0 && kout < nf) {
+        kov[i] = kout;
+        ipv[i] = inv_phihat[mm < 0 ? -mm : mm];
+      }
+    }
+  }
+  lds_fft<EMAX, NT>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
+#pragma unroll
+  for (int i = 0; i < PO; ++i) {
+    const int64_t kout = kov[i];
+    if (kout < 0) continue;
+    const int e = tid + i * NT;
+    const int d = e % D;
+    const int k = e / D;
+    const double ip = ipv[i];
     if (G == 3) {
       const T2 A = buf[(0 * D + d) * Lp + k];
       const T2 B = buf[(1 * D + d) * Lp + k];
@@ -406,7 +427,7 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
                       (double)B.y * ip,  (double)B2.x * ip, (double)B2.y * ip};
       const int64_t q = kout - st.k_lo;
       if (lowfix && q >= 0 && q < st.nlow)
-        for (int i = 0; i < 6; ++i) s6[i] = lowfix[6 * q + i];
+        for (int j = 0; j < 6; ++j) s6[j] = lowfix[6 * q + j];
       double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean);
       if (kout == a.kzero) pw = 0.0;
       a.power[kout] = pw;
