@@ -164,6 +164,7 @@ __device__ void bins_block(const CallArgs& a, const Plan& p, const Work& w, DevS
   for (int j = tid; j < nd; j += NT) {
     const double t = a.t[j];
     const int pos = atomicAdd(&w.bin_cursor[point_bin(t, tau, a.df, p)], 1);
+    if (pos < 0 || pos >= nd) continue;  // cannot happen with a consistent histogram
     w.ts[pos] = t;
     w.ys[pos] = a.y[j];
     w.dys[pos] = a.dy ? a.dy[j] : 1.0;
@@ -192,7 +193,7 @@ __device__ __noinline__ void batch_lowfreq(const CallArgs& a, DevStats* st, doub
   double acc[6 * kLowGroup];
   for (int g0 = 0; g0 < nlow; g0 += kLowGroup) {
     const int ng = nlow - g0 < kLowGroup ? nlow - g0 : kLowGroup;
-    low_accumulate(a, s, k_lo + g0, ng, threadIdx.x, NT, acc);
+    low_accumulate<kLowGroup>(a, s, k_lo + g0, ng, threadIdx.x, NT, acc);
     block_sum<NT, 6 * kLowGroup>(acc, red, lowfix + 6 * g0);
   }
   if (threadIdx.x == 0) {

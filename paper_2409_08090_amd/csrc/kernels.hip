@@ -160,10 +160,16 @@ __global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
 // counting sort below rebuilds everything.
 __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Work w) {
   const DevStats* st = w.stats;
-  if (st->status != 0 || st->need_sort) return;
-  const double tau = st->tau;
+  if (st->status != 0) return;
   const int nd = (int)a.nd;
   const int nb = (int)p.nbins;
+  // The histogram of the counting sort is cleared by every block, before any
+  // early exit: need_sort may be raised by another block of this launch.
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i <= nb;
+       i += (int64_t)gridDim.x * kThreads)
+    w.bin_count[i] = 0;
+  if (st->need_sort) return;
+  const double tau = st->tau;
   const int64_t total = nd > nb + 1 ? nd : nb + 1;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kThreads) {
@@ -183,14 +189,6 @@ __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Wo
       w.bin_start[b] = lo;
     }
   }
-}
-
-__global__ __launch_bounds__(kThreads) void k_sort_fill(Plan p, Work w) {
-  const DevStats* st = w.stats;
-  if (st->status != 0 || !st->need_sort) return;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i <= p.nbins;
-       i += (int64_t)gridDim.x * kThreads)
-    w.bin_count[i] = 0;
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_hist(CallArgs a, Plan p, Work w) {
@@ -236,34 +234,22 @@ __global__ __launch_bounds__(kThreads) void k_scan1(Plan p, Work w) {
   if (threadIdx.x == kThreads - 1) w.scan_part[blockIdx.x] = s[kThreads - 1];
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan2(int64_t nchunks, Work w) {
-  const DevStats* st = w.stats;
-  if (st->status != 0 || !st->need_sort) return;
-  __shared__ int s[kThreads];
-  int carry = 0;
-  for (int64_t base = 0; base < nchunks; base += kThreads) {
-    int64_t i = base + threadIdx.x;
-    int v = i < nchunks ? w.scan_part[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-      int x = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-      __syncthreads();
-      s[threadIdx.x] += x;
-      __syncthreads();
-    }
-    if (i < nchunks) w.scan_part[i] = carry + s[threadIdx.x] - v;
-    int tot = s[kThreads - 1];
-    __syncthreads();
-    carry += tot;
-  }
-}
-
+// Offsets of the per-chunk scans: block b adds the totals of chunks 0..b-1
+// (a few hundred values) to its chunk.
 __global__ __launch_bounds__(kThreads) void k_scan3(Plan p, Work w) {
   const DevStats* st = w.stats;
   if (st->status != 0 || !st->need_sort) return;
+  __shared__ int red[kThreads];
+  int part = 0;
+  for (unsigned b = threadIdx.x; b < blockIdx.x; b += kThreads) part += w.scan_part[b];
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int sft = kThreads / 2; sft > 0; sft >>= 1) {
+    if ((int)threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
+    __syncthreads();
+  }
+  const int add = red[0];
   const int64_t cnt = p.nbins + 1;
-  const int add = w.scan_part[blockIdx.x];
   for (int q = 0; q < 8; ++q) {
     int64_t i = (int64_t)blockIdx.x * kScanChunk + q * kThreads + threadIdx.x;
     if (i < cnt) {
@@ -282,6 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
        j += (int64_t)gridDim.x * kThreads) {
     double t = a.t[j];
     int pos = atomicAdd(&w.bin_cursor[point_bin(t, tau, a.df, p)], 1);
+    if (pos < 0 || pos >= a.nd) continue;  // cannot happen with a consistent histogram
     w.ts[pos] = t;
     if (a.periodogram) {
       w.ys[pos] = a.y[j];
@@ -344,11 +331,13 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
 }
 
 // Direct FP64 sums A, B, B2 at the (at most kLowMax) frequencies nearest
-// f = 0 with |f| span < 2.  Blocks stride over the points; partials go to
-// lowpart and the last block to finish adds them up into lowfix.
+// f = 0 with |f| span < 2, all of them in one sweep over the points.  Blocks
+// stride over the points; partials go to lowpart and the last block to
+// finish adds them up into lowfix.
 __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
-  __shared__ double red[(kThreads / 64) * 6 * kLowGroup];
-  __shared__ double tot[6 * kLowGroup];
+  constexpr int NV = 6 * kLowMax;
+  __shared__ double red[(kThreads / 64) * NV];
+  __shared__ double tot[NV];
   __shared__ bool amLast;
   DevStats* stp = w.stats;
   if (stp->status != 0 || !a.periodogram) return;
@@ -357,14 +346,11 @@ __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
   int nlow;
   low_band(st, a.f0, a.df, a.nf, k_lo, nlow);
   if (nlow == 0) return;
-  double acc[6 * kLowGroup];
-  for (int g0 = 0; g0 < nlow; g0 += kLowGroup) {
-    const int ng = nlow - g0 < kLowGroup ? nlow - g0 : kLowGroup;
-    low_accumulate(a, st, k_lo + g0, ng, (int64_t)blockIdx.x * kThreads + threadIdx.x,
-                   (int64_t)gridDim.x * kThreads, acc);
-    block_sum<kThreads, 6 * kLowGroup>(acc, red, tot);
-    if ((int)threadIdx.x < 6 * ng) w.lowpart[(size_t)blockIdx.x * 6 * kLowMax + 6 * g0 + threadIdx.x] = tot[threadIdx.x];
-  }
+  double acc[NV];
+  low_accumulate<kLowMax>(a, st, k_lo, nlow, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+                          (int64_t)gridDim.x * kThreads, acc);
+  block_sum<kThreads, NV>(acc, red, tot);
+  if ((int)threadIdx.x < NV) w.lowpart[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();
@@ -374,19 +360,14 @@ __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
   __syncthreads();
   if (!amLast) return;
   __threadfence();
-  // thread b holds partial b (gridDim.x <= kThreads); one block-wide sum per value
-  double v[6 * kLowMax];
-  const bool have = threadIdx.x < gridDim.x;
+  // thread b adds partials b, b + kThreads, ...; then one block-wide sum per value
 #pragma unroll
-  for (int i = 0; i < 6 * kLowMax; ++i)
-    v[i] = (have && i < 6 * nlow) ? w.lowpart[(size_t)threadIdx.x * 6 * kLowMax + i] : 0.0;
-  __shared__ double red2[(kThreads / 64) * 6 * kLowGroup];
+  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += kThreads)
 #pragma unroll
-  for (int g0 = 0; g0 < kLowMax; g0 += kLowGroup) {
-    block_sum<kThreads, 6 * kLowGroup>(v + 6 * g0, red2, tot);
-    if ((int)threadIdx.x < 6 * kLowGroup && 6 * g0 + (int)threadIdx.x < 6 * nlow)
-      w.lowfix[6 * g0 + threadIdx.x] = tot[threadIdx.x];
-  }
+    for (int i = 0; i < NV; ++i) acc[i] += w.lowpart[(size_t)b * NV + i];
+  block_sum<kThreads, NV>(acc, red, tot);
+  if ((int)threadIdx.x < 6 * nlow) w.lowfix[threadIdx.x] = tot[threadIdx.x];
   if (threadIdx.x == 0) {
     stp->k_lo = k_lo;
     stp->nlow = nlow;
@@ -441,18 +422,15 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
   if (a.periodogram)
     hipLaunchKernelGGL(k_lowfreq, dim3(grid_for(a.nd, kLowBlocks)), dim3(kThreads), 0, s, a, w);
-  static_assert(kLowBlocks <= kThreads, "one partial per thread in the final sum");
   mark(kStageStats, 0);
   mark(kStageBin, 1);
   const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
   hipLaunchKernelGGL(k_bins_sorted, dim3(grid_for(nbt, 1 << 20)), dim3(kThreads), 0, s, a, p, w);
   // counting-sort path: these exit at once unless a descent was found
   const unsigned sort_blocks = grid_for(a.nd > p.nbins ? a.nd : p.nbins, 512);
-  hipLaunchKernelGGL(k_sort_fill, dim3(sort_blocks), dim3(kThreads), 0, s, p, w);
   hipLaunchKernelGGL(k_sort_hist, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
   const int64_t nchunks = (p.nbins + 1 + kScanChunk - 1) / kScanChunk;
   hipLaunchKernelGGL(k_scan1, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
-  hipLaunchKernelGGL(k_scan2, dim3(1), dim3(kThreads), 0, s, nchunks, w);
   hipLaunchKernelGGL(k_scan3, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
   hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
   mark(kStageBin, 0);

@@ -111,7 +111,7 @@ struct Work {
   double* lowfix;         // direct sums A, B, B2 near f = 0 (kLowMax x 6)
 };
 
-constexpr int kStatsBlocks = 512;
+constexpr int kStatsBlocks = 1024;
 constexpr int kThreads = 256;       // threads of most kernels
 constexpr int kThreadsLast = 512;   // threads of the last FFT pass
 constexpr int kTileMax = 1024;      // spreading tile (cells)
@@ -128,6 +128,6 @@ constexpr int kBatchLds = 65536;    // dynamic LDS of the batched kernel
 // from the transform's band edge.
 constexpr int kLowMax = 16;
 constexpr int kLowGroup = 8;
-constexpr int kLowBlocks = 256;
+constexpr int kLowBlocks = 1024;
 
 }  // namespace mils

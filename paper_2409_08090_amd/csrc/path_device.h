@@ -278,12 +278,23 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
     const int e = tid + i * NT;
     if (e < E) buf[e] = v[i];
   }
-  __syncthreads();
-  lds_fft<EMAX, NT>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
+  // Inter-pass twiddles exp(2 pi i s k / N) of this thread's outputs,
+  // started before the transform so that their latency overlaps it.  The
+  // thread's outputs share the column s and their k steps by NT/C, so all of
+  // them follow from two table values (first k, step) by multiplication.
   const int64_t mask = ((int64_t)1 << ps.bshift) - 1;
   const T2* tlo = tw + ps.twlo_off;
   const T2* thi = tw + ps.twhi_off;
+  const int64_t Ntw = (int64_t)L * S;
+  const int64_t scol = s0 + (tid & (C - 1));
+  const int64_t q0 = (scol * (int64_t)(tid >> csh)) % Ntw;  // rows past L are unused
+  const int64_t qs = (scol * (int64_t)(NT >> csh)) % Ntw;
+  const T2 w0 = cmul(thi[q0 >> ps.bshift], tlo[q0 & mask]);
+  const T2 ws = cmul(thi[qs >> ps.bshift], tlo[qs & mask]);
+  __syncthreads();
+  lds_fft<EMAX, NT>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
   const int64_t PS = P * S;
+  T2 tk = w0;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
     const int e = tid + i * NT;
@@ -292,12 +303,10 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
       const int c = e & (C - 1);
       if (c < ceff) {
         const int64_t s = s0 + c;
-        T2 x = buf[e];
-        const int64_t q = s * k;
-        if (q) x = cmul(x, cmul(thi[q >> ps.bshift], tlo[q & mask]));
-        out[(int64_t)k * PS + pidx * S + s] = x;
+        out[(int64_t)k * PS + pidx * S + s] = cmul(buf[e], tk);
       }
     }
+    tk = cmul(tk, ws);
   }
   __syncthreads();
 }
@@ -477,11 +486,12 @@ __device__ __forceinline__ void low_band(const DevStats& st, double f0, double d
 // q < kLowGroup, summed over points j = j0, j0 + stride, ... < nd.  The phase
 // at the first frequency is reduced in double-double; the others follow by
 // the exact angle-sum recurrence with the step exp(i 2 pi df t).
+template <int GRP>
 __device__ __forceinline__ void low_accumulate(const CallArgs& a, const DevStats& st, int64_t k_first,
                                                int ng, int64_t j0, int64_t stride,
-                                               double* acc /* 6 * kLowGroup */) {
+                                               double* acc /* 6 * GRP */) {
 #pragma unroll
-  for (int i = 0; i < 6 * kLowGroup; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 6 * GRP; ++i) acc[i] = 0.0;
   // f_first = f0 + k_first df as a double-double
   double kp, ke;
   dd_two_prod((double)k_first, a.df, kp, ke);
@@ -502,7 +512,7 @@ __device__ __forceinline__ void low_accumulate(const CallArgs& a, const DevStats
     prephase(t, st.tau, fh, fl, pc, ps);
     prephase(t, st.tau, a.df, 0.0, sc, ss);
 #pragma unroll
-    for (int q = 0; q < kLowGroup; ++q) {
+    for (int q = 0; q < GRP; ++q) {
       if (q < ng) {
         const double c2 = pc * pc - ps * ps, s2 = 2.0 * pc * ps;
         acc[6 * q + 0] += wy * pc;

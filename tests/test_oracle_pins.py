@@ -251,14 +251,17 @@ def test_standard_power_invariant_to_affine_y(s, scale, offset):
 def test_power_invariant_to_dy_scale_and_permutation(s, scale):
     n, seed = s
     rng, t, y, dy = _series(n, seed)
+    pstd = oracle.periodogram(t, y, dy, 0.002, 0.017, nf=30)
+    perm = rng.permutation(n)
     for norm in ("standard", "model", "log"):
         a = oracle.periodogram(t, y, dy, 0.002, 0.017, nf=30, normalization=norm)
         b = oracle.periodogram(t, y, dy * scale, 0.002, 0.017, nf=30, normalization=norm)
-        perm = rng.permutation(n)
         c = oracle.periodogram(t[perm], y[perm], dy[perm], 0.002, 0.017, nf=30,
                                normalization=norm)
-        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
-        np.testing.assert_allclose(a, c, rtol=1e-9, atol=1e-12)
+        # model and log are functions of 1 - P_std, whose rounding they amplify
+        rtol = 1e-9 if norm == "standard" else 1e-9 / np.maximum(1.0 - pstd, 1e-6)
+        assert np.all(np.abs(a - b) <= rtol * np.abs(a) + 1e-12)
+        assert np.all(np.abs(a - c) <= rtol * np.abs(a) + 1e-12)
 
 
 def test_time_and_frequency_rescaling():
