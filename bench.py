@@ -245,11 +245,12 @@ def main():
         import oracle
         rng = np.random.default_rng(2)
         # calibrate the sample size on a few frequencies, then time the sample
-        k0 = rng.integers(0, c.nf, 8)
+        oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=rng.integers(0, c.nf, 8))  # thread start-up
+        k0 = rng.integers(0, c.nf, 64)
         s0 = time.perf_counter()
         oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k0)
         per = (time.perf_counter() - s0) / k0.size
-        nk = int(max(16, min(4000, args.cpu_seconds / max(per, 1e-6))))
+        nk = int(max(16, min(40000, args.cpu_seconds / max(per, 1e-6))))
         top = np.argsort(power.cpu().numpy())[-20:]
         ks = np.unique(np.concatenate([rng.integers(0, c.nf, nk), top]))
         s1 = time.perf_counter()

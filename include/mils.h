@@ -99,6 +99,8 @@ typedef struct {
   int32_t tile;        /* spreading tile, in cells */
   int32_t bin;         /* point-binning granularity, in cells */
   uint64_t workspace_bytes; /* device workspace the call needs */
+  int32_t last_rows;   /* rows of length len[npass-1] per workgroup of the last pass */
+  int32_t last_lds_bytes; /* dynamic LDS of one workgroup of the last pass */
 } mils_plan_desc;
 
 /* Library version (MILS_VERSION of the build). */

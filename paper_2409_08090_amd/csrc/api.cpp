@@ -430,6 +430,12 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
   out->tile = pl.T;
   out->bin = pl.Tb;
   out->workspace_bytes = layout_work(pl, nd, 3, nullptr, nullptr);
+  {
+    const FftPass& lp = pl.pass[pl.npass - 1];
+    out->last_rows = lp.C;
+    out->last_lds_bytes = (int32_t)((pl.prec == 1 ? 8 : 16) *
+                                    ((size_t)lp.L * last_pitch(3 * lp.C) + lp.L));
+  }
   return MILS_OK;
 }
 

@@ -112,88 +112,106 @@ __device__ __forceinline__ void dft(T2* a) {
   else if constexpr (R == 8) dft8(a);
 }
 
-// One Stockham stage of radix R over `ncol` columns of length L held in LDS.
-// Ns = product of the radices of the earlier stages.  twL[x] = exp(2 pi i x / L).
-// jfast selects the thread mapping: consecutive threads take consecutive
-// butterflies of one column (columns contiguous in LDS) or the same butterfly
-// of consecutive columns (elements of a row contiguous in LDS).
+// Quotient floor(j / d) for 0 <= j < 2048, 1 <= d <= 1024, given
+// r = fdiv_recip(d): a float product and a truncation (exact over that range
+// even with the reciprocal 2 ulp off; checked exhaustively on the host).
+__device__ __forceinline__ float fdiv_recip(int d) {
+  return __builtin_amdgcn_rcpf((float)d) * 1.000244140625f;
+}
+__device__ __forceinline__ int fdiv_small(int j, float r) { return (int)((float)j * r); }
+
+// Per-thread walk over the butterflies (or elements) idx = tid + b*NT of a
+// set of ncol columns, idx = j*ncol + col: the first (j, col) takes one
+// division, each later one a few adds (NT = qn*ncol + rn with rn < ncol).
+struct ColWalk {
+  int j, col, qn, rn, ncol;
+  __device__ __forceinline__ ColWalk(int tid, int nt, int nc) : ncol(nc) {
+    j = tid / nc;
+    col = tid - j * nc;
+    qn = nt / nc;
+    rn = nt - qn * nc;
+  }
+  __device__ __forceinline__ void next() {
+    col += rn;
+    j += qn;
+    if (col >= ncol) {
+      col -= ncol;
+      ++j;
+    }
+  }
+};
+
+// One Stockham stage of radix R over `ncol` columns of length L held in LDS;
+// element l of column c sits at buf[c + l*ls] (ls >= ncol).  Ns = product of
+// the radices of the earlier stages.  twL[x] = exp(2 pi i x / L).  A thread
+// takes butterflies j of column col as given by the walk (consecutive threads:
+// consecutive columns of one butterfly, so the R reads and writes of a wave
+// are runs of ncol contiguous elements).  All index arithmetic is 32-bit with
+// 24-bit products: L <= 1024 and ls * L fits easily.
 template <int R, int MAXB, int NT, typename T2>
-__device__ __forceinline__ void stockham_stage(T2* buf, int L, int ncol, int cs, int ls, int Ns,
-                                               const T2* twL, bool jfast) {
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void stockham_stage(T2* buf, int L, int ls, int Ns, const T2* twL,
+                                               ColWalk w) {
   const int nb = L / R;
-  const int total = nb * ncol;
   const int twstride = L / (Ns * R);
+  const float rNs = fdiv_recip(Ns);
+  const int rstep = nb * ls;       // between the R inputs of a butterfly
+  const int wstep = Ns * ls;       // between its R outputs
   T2 v[MAXB][R];
+  int wofs[MAXB];
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
-    int idx = tid + b * NT;
-    if (idx < total) {
-      int col, j;
-      if (jfast) {
-        col = idx / nb;
-        j = idx - col * nb;
-      } else {
-        j = idx / ncol;
-        col = idx - j * ncol;
-      }
-      int k = j % Ns;
-      const T2* base = buf + col * cs;
+    wofs[b] = -1;
+    if (w.j < nb) {
+      const int jq = fdiv_small(w.j, rNs);
+      const int k = w.j - __mul24(jq, Ns);
+      const int rofs = w.col + __mul24(w.j, ls);
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[b][q] = base[(j + q * nb) * ls];
+      for (int q = 0; q < R; ++q) v[b][q] = buf[rofs + q * rstep];
       if (Ns > 1) {
+        const int kt = __mul24(k, twstride);
 #pragma unroll
-        for (int q = 1; q < R; ++q) v[b][q] = cmul(v[b][q], twL[q * k * twstride]);
+        for (int q = 1; q < R; ++q) v[b][q] = cmul(v[b][q], twL[q * kt]);
       }
       dft<R>(v[b]);
+      wofs[b] = w.col + __mul24(__mul24(jq, Ns * R) + k, ls);
     }
+    w.next();
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < MAXB; ++b) {
-    int idx = tid + b * NT;
-    if (idx < total) {
-      int col, j;
-      if (jfast) {
-        col = idx / nb;
-        j = idx - col * nb;
-      } else {
-        j = idx / ncol;
-        col = idx - j * ncol;
-      }
-      int k = j % Ns;
-      int dst = (j - k) * R + k;
-      T2* base = buf + col * cs;
+    if (wofs[b] >= 0) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) base[(dst + q * Ns) * ls] = v[b][q];
+      for (int q = 0; q < R; ++q) buf[wofs[b] + q * wstep] = v[b][q];
     }
   }
   __syncthreads();
 }
 
-// Full transform of all columns: runs the stages of the radix plan.
+// Full transform of the ncol columns: runs the stages of the radix plan.
 // EMAX bounds L * ncol (it sizes the per-thread register arrays).
 template <int EMAX, int NT, typename T2>
-__device__ void lds_fft(T2* buf, int L, int ncol, int cs, int ls, const int* rad, int nrad,
-                        const T2* twL, bool jfast) {
+__device__ __forceinline__ void lds_fft(T2* buf, int L, int ncol, int ls, const int* rad, int nrad,
+                        const T2* twL) {
+  const ColWalk w(threadIdx.x, NT, ncol);
   int Ns = 1;
   for (int s = 0; s < nrad; ++s) {
     int r = rad[s];
     switch (r) {
       case 2:
-        stockham_stage<2, (EMAX / 2 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        stockham_stage<2, (EMAX / 2 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
         break;
       case 3:
-        stockham_stage<3, (EMAX / 3 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        stockham_stage<3, (EMAX / 3 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
         break;
       case 4:
-        stockham_stage<4, (EMAX / 4 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        stockham_stage<4, (EMAX / 4 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
         break;
       case 5:
-        stockham_stage<5, (EMAX / 5 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        stockham_stage<5, (EMAX / 5 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
         break;
       default:
-        stockham_stage<8, (EMAX / 8 + NT - 1) / NT, NT>(buf, L, ncol, cs, ls, Ns, twL, jfast);
+        stockham_stage<8, (EMAX / 8 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
         break;
     }
     Ns *= r;

@@ -21,17 +21,56 @@ namespace mils {
 
 // ============================================================================
 // Statistics: weighted mean/variance (merged Welford moments), time range,
-// sortedness and validity.  One launch; the last block to finish combines the
-// per-block partials and writes the scalars of the call.
+// sortedness and validity.  k_stats leaves one partial per block; the one-block
+// k_stats_final combines them in a fixed order and writes the scalars of the
+// call.  (Two launches instead of a last-block-done counter: the device-scope
+// fence such a counter needs is paid by every block.)
 // ============================================================================
-__global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
+struct StatsPart {
+  Moments m;
+  double lo, hi;
+  int bad, uns;
+};
+
+// Block-wide combine of one StatsPart per thread; thread 0 gets the total.
+__device__ __forceinline__ StatsPart stats_block_combine(StatsPart x) {
   __shared__ double sW[kThreads], sMu[kThreads], sM2[kThreads], sLo[kThreads], sHi[kThreads];
   __shared__ int sBad[kThreads], sUns[kThreads];
-  __shared__ bool amLast;
   const int tid = threadIdx.x;
-  Moments m = {0.0, 0.0, 0.0};
-  double lo = INFINITY, hi = -INFINITY;
-  int bad = 0, uns = 0;
+  sW[tid] = x.m.W;
+  sMu[tid] = x.m.mu;
+  sM2[tid] = x.m.M2;
+  sLo[tid] = x.lo;
+  sHi[tid] = x.hi;
+  sBad[tid] = x.bad;
+  sUns[tid] = x.uns;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      Moments y = {sW[tid], sMu[tid], sM2[tid]};
+      moments_merge(y, sW[tid + s], sMu[tid + s], sM2[tid + s]);
+      sW[tid] = y.W;
+      sMu[tid] = y.mu;
+      sM2[tid] = y.M2;
+      sLo[tid] = fmin(sLo[tid], sLo[tid + s]);
+      sHi[tid] = fmax(sHi[tid], sHi[tid + s]);
+      sBad[tid] |= sBad[tid + s];
+      sUns[tid] |= sUns[tid + s];
+    }
+    __syncthreads();
+  }
+  StatsPart r;
+  r.m = {sW[0], sMu[0], sM2[0]};
+  r.lo = sLo[0];
+  r.hi = sHi[0];
+  r.bad = sBad[0];
+  r.uns = sUns[0];
+  return r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
+  const int tid = threadIdx.x;
+  StatsPart x = {{0.0, 0.0, 0.0}, INFINITY, -INFINITY, 0, 0};
   const double* yv = a.periodogram ? a.y : a.h;
   for (int64_t j = (int64_t)blockIdx.x * kThreads + tid; j < a.nd; j += (int64_t)gridDim.x * kThreads) {
     double t = a.t[j];
@@ -39,113 +78,63 @@ __global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
     double wj = 1.0;
     if (a.dy) {
       double d = a.dy[j];
-      if (!(d > 0.0) || !isfinite(d)) bad = 1;
+      if (!(d > 0.0) || !isfinite(d)) x.bad = 1;
       wj = 1.0 / (d * d);
     }
-    if (!isfinite(t) || !isfinite(y) || !isfinite(wj)) bad = 1;
-    if (j > 0 && t < a.t[j - 1]) uns = 1;
-    lo = fmin(lo, t);
-    hi = fmax(hi, t);
-    moments_merge(m, wj, y, 0.0);
+    if (!isfinite(t) || !isfinite(y) || !isfinite(wj)) x.bad = 1;
+    if (j > 0 && t < a.t[j - 1]) x.uns = 1;
+    x.lo = fmin(x.lo, t);
+    x.hi = fmax(x.hi, t);
+    moments_merge(x.m, wj, y, 0.0);
   }
-  sW[tid] = m.W;
-  sMu[tid] = m.mu;
-  sM2[tid] = m.M2;
-  sLo[tid] = lo;
-  sHi[tid] = hi;
-  sBad[tid] = bad;
-  sUns[tid] = uns;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      Moments x = {sW[tid], sMu[tid], sM2[tid]};
-      moments_merge(x, sW[tid + s], sMu[tid + s], sM2[tid + s]);
-      sW[tid] = x.W;
-      sMu[tid] = x.mu;
-      sM2[tid] = x.M2;
-      sLo[tid] = fmin(sLo[tid], sLo[tid + s]);
-      sHi[tid] = fmax(sHi[tid], sHi[tid + s]);
-      sBad[tid] |= sBad[tid + s];
-      sUns[tid] |= sUns[tid + s];
-    }
-    __syncthreads();
-  }
+  const StatsPart r = stats_block_combine(x);
   if (tid == 0) {
     double* p = w.partials + 8 * blockIdx.x;
-    p[0] = sW[0];
-    p[1] = sMu[0];
-    p[2] = sM2[0];
-    p[3] = sLo[0];
-    p[4] = sHi[0];
-    p[5] = (double)sBad[0];
-    p[6] = (double)sUns[0];
-    __threadfence();
-    unsigned int prev = atomicAdd(&w.stats->done, 1u);
-    amLast = (prev == gridDim.x - 1);
+    p[0] = r.m.W;
+    p[1] = r.m.mu;
+    p[2] = r.m.M2;
+    p[3] = r.lo;
+    p[4] = r.hi;
+    p[5] = (double)r.bad;
+    p[6] = (double)r.uns;
   }
-  __syncthreads();
-  if (!amLast) return;
-  __threadfence();
-  // final combine over the per-block partials
-  m = {0.0, 0.0, 0.0};
-  lo = INFINITY;
-  hi = -INFINITY;
-  bad = 0;
-  uns = 0;
-  for (int b = tid; b < (int)gridDim.x; b += kThreads) {
-    const volatile double* p = w.partials + 8 * b;
-    moments_merge(m, p[0], p[1], p[2]);
-    lo = fmin(lo, p[3]);
-    hi = fmax(hi, p[4]);
-    bad |= (p[5] != 0.0);
-    uns |= (p[6] != 0.0);
+}
+
+__global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, int nparts) {
+  const int tid = threadIdx.x;
+  StatsPart x = {{0.0, 0.0, 0.0}, INFINITY, -INFINITY, 0, 0};
+  for (int b = tid; b < nparts; b += kThreads) {
+    const double* p = w.partials + 8 * b;
+    moments_merge(x.m, p[0], p[1], p[2]);
+    x.lo = fmin(x.lo, p[3]);
+    x.hi = fmax(x.hi, p[4]);
+    x.bad |= (p[5] != 0.0);
+    x.uns |= (p[6] != 0.0);
   }
-  sW[tid] = m.W;
-  sMu[tid] = m.mu;
-  sM2[tid] = m.M2;
-  sLo[tid] = lo;
-  sHi[tid] = hi;
-  sBad[tid] = bad;
-  sUns[tid] = uns;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      Moments x = {sW[tid], sMu[tid], sM2[tid]};
-      moments_merge(x, sW[tid + s], sMu[tid + s], sM2[tid + s]);
-      sW[tid] = x.W;
-      sMu[tid] = x.mu;
-      sM2[tid] = x.M2;
-      sLo[tid] = fmin(sLo[tid], sLo[tid + s]);
-      sHi[tid] = fmax(sHi[tid], sHi[tid + s]);
-      sBad[tid] |= sBad[tid + s];
-      sUns[tid] |= sUns[tid + s];
-    }
-    __syncthreads();
-  }
+  const StatsPart r = stats_block_combine(x);
   if (tid == 0) {
     DevStats* st = w.stats;
-    st->W = sW[0];
-    st->mu = sMu[0];
-    st->M2 = sM2[0];
-    st->tmin = sLo[0];
-    st->tmax = sHi[0];
-    st->invalid = sBad[0];
-    st->unsorted = sUns[0];
-    st->need_sort = sUns[0];
-    st->tau = a.periodogram ? sLo[0] : 0.0;
-    double W = sW[0];
-    st->ysub = a.center ? sMu[0] : 0.0;
-    st->Ybar = a.center ? 0.0 : sMu[0];
-    double YY = sM2[0] / W;
-    if (!a.fit_mean && !a.center) YY += sMu[0] * sMu[0];
+    st->W = r.m.W;
+    st->mu = r.m.mu;
+    st->M2 = r.m.M2;
+    st->tmin = r.lo;
+    st->tmax = r.hi;
+    st->invalid = r.bad;
+    st->unsorted = r.uns;
+    st->need_sort = r.uns;
+    st->tau = a.periodogram ? r.lo : 0.0;
+    const double W = r.m.W;
+    st->ysub = a.center ? r.m.mu : 0.0;
+    st->Ybar = a.center ? 0.0 : r.m.mu;
+    double YY = r.m.M2 / W;
+    if (!a.fit_mean && !a.center) YY += r.m.mu * r.m.mu;
     st->YY = YY;
     int status = 0;
-    if (sBad[0]) status = -1;
+    if (r.bad) status = -1;
     else if (a.periodogram && !(YY > 0.0)) status = -2;
     st->status = status;
     st->nlow = 0;
     st->k_lo = 0;
-    st->done = 0u;
   }
 }
 
@@ -332,46 +321,67 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
 
 // Direct FP64 sums A, B, B2 at the (at most kLowMax) frequencies nearest
 // f = 0 with |f| span < 2, all of them in one sweep over the points.  Blocks
-// stride over the points; partials go to lowpart and the last block to
-// finish adds them up into lowfix.
+// stride over the points and leave their totals in lowpart; the one-block
+// k_lowfreq_final adds them up into lowfix.  Block totals are formed by a
+// transpose through LDS, kLowChunk values at a time: every value is then
+// summed by 8 threads over 32 entries each, and the 8 parts are combined
+// across lanes (a fixed order, so the result does not depend on timing).
+constexpr int kLowChunk = 32;
+constexpr int kLowStride = kThreads + 8;  // row pitch: spreads the 8 parts over the banks
+constexpr int kLowNV = 6 * kLowMax;
 __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
-  constexpr int NV = 6 * kLowMax;
-  __shared__ double red[(kThreads / 64) * NV];
-  __shared__ double tot[NV];
-  __shared__ bool amLast;
-  DevStats* stp = w.stats;
-  if (stp->status != 0 || !a.periodogram) return;
-  const DevStats st = *stp;
+  static_assert(kLowNV % kLowChunk == 0 && kLowChunk * 8 == kThreads, "transpose shape");
+  __shared__ double red[kLowChunk * kLowStride];
+  const DevStats st = *w.stats;
+  if (st.status != 0 || !a.periodogram) return;
   int64_t k_lo;
   int nlow;
   low_band(st, a.f0, a.df, a.nf, k_lo, nlow);
   if (nlow == 0) return;
-  double acc[NV];
-  low_accumulate<kLowMax>(a, st, k_lo, nlow, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+  const int tid = threadIdx.x;
+  double acc[kLowNV];
+  low_accumulate<kLowMax>(a, st, k_lo, nlow, (int64_t)blockIdx.x * kThreads + tid,
                           (int64_t)gridDim.x * kThreads, acc);
-  block_sum<kThreads, NV>(acc, red, tot);
-  if ((int)threadIdx.x < NV) w.lowpart[(size_t)blockIdx.x * NV + threadIdx.x] = tot[threadIdx.x];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&stp->done, 1u);
-    amLast = (prev == gridDim.x - 1);
+  const int v = tid >> 3, part = tid & 7;
+#pragma unroll
+  for (int c = 0; c < kLowNV; c += kLowChunk) {
+#pragma unroll
+    for (int i = 0; i < kLowChunk; ++i) red[i * kLowStride + tid] = acc[c + i];
+    __syncthreads();
+    double sum = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < kThreads / 8; ++i) sum += red[v * kLowStride + part + 8 * i];
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 4, 64);
+    if (part == 0) w.lowpart[(size_t)blockIdx.x * kLowNV + c + v] = sum;
+    __syncthreads();
   }
-  __syncthreads();
-  if (!amLast) return;
-  __threadfence();
-  // thread b adds partials b, b + kThreads, ...; then one block-wide sum per value
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += kThreads)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += w.lowpart[(size_t)b * NV + i];
-  block_sum<kThreads, NV>(acc, red, tot);
-  if ((int)threadIdx.x < 6 * nlow) w.lowfix[threadIdx.x] = tot[threadIdx.x];
-  if (threadIdx.x == 0) {
+}
+
+// value x = idx / 8 is summed over blocks b = idx % 8 (mod 8) by one thread,
+// then over the 8 lanes that hold its parts
+__global__ __launch_bounds__(kThreads) void k_lowfreq_final(CallArgs a, Work w, int nparts) {
+  DevStats* stp = w.stats;
+  const DevStats st = *stp;
+  if (st.status != 0 || !a.periodogram) return;
+  int64_t k_lo;
+  int nlow;
+  low_band(st, a.f0, a.df, a.nf, k_lo, nlow);
+  if (nlow == 0) return;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kLowNV * 8; idx += kThreads) {
+    const int x = idx >> 3, pr = idx & 7;
+    double sum = 0.0;
+    for (int b = pr; b < nparts; b += 8) sum += w.lowpart[(size_t)b * kLowNV + x];
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 4, 64);
+    if (pr == 0 && x < 6 * nlow) w.lowfix[x] = sum;
+  }
+  if (tid == 0) {
     stp->k_lo = k_lo;
     stp->nlow = nlow;
-    stp->done = 0u;
   }
 }
 
@@ -420,8 +430,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   };
   mark(kStageStats, 1);
   hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
-  if (a.periodogram)
-    hipLaunchKernelGGL(k_lowfreq, dim3(grid_for(a.nd, kLowBlocks)), dim3(kThreads), 0, s, a, w);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kThreads), 0, s, a, w, kStatsBlocks);
+  if (a.periodogram) {
+    const unsigned lb = grid_for(a.nd, kLowBlocks);
+    hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s, a, w);
+    hipLaunchKernelGGL(k_lowfreq_final, dim3(1), dim3(kThreads), 0, s, a, w, (int)lb);
+  }
   mark(kStageStats, 0);
   mark(kStageBin, 1);
   const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
@@ -490,7 +504,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.rowflag[g] = nullptr;
     }
     const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
-    const size_t lds = sizeof(T2) * (size_t)(G * ps.C * (ps.L + 1) + ps.L);
+    const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ps.L);
     mark(kStageLast, 1);
     if (a.periodogram)
       hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, kThreadsLast>), dim3((unsigned)nblk),

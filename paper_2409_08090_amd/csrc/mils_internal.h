@@ -66,7 +66,6 @@ struct DevStats {
   int unsorted;    // t not non-decreasing
   int need_sort;   // points must go through the counting sort
   int status;      // 0 ok, -1 invalid input, -2 degenerate (YY == 0)
-  unsigned int done;  // last-block counter of the reduction (self-resetting)
   int nlow;        // frequencies evaluated directly near f = 0 (see lowfix)
   int64_t k_lo;    // first of them
 };
@@ -128,6 +127,10 @@ constexpr int kBatchLds = 65536;    // dynamic LDS of the batched kernel
 // from the transform's band edge.
 constexpr int kLowMax = 16;
 constexpr int kLowGroup = 8;
-constexpr int kLowBlocks = 1024;
+constexpr int kLowBlocks = 512;
+
+// LDS pitch of the last FFT pass: its rows are interleaved element by element
+// with no padding.
+__host__ __device__ constexpr inline int last_pitch(int rows) { return rows; }
 
 }  // namespace mils

@@ -234,10 +234,11 @@ struct PassBufs {
 // A first/middle pass: workgroup = C consecutive columns s of one outer index
 // p; loads L x C elements (C contiguous per row, 128-256 B segments),
 // transforms along L in LDS, applies the inter-pass twiddle and stores with
-// the outer index and k transposed.  Dynamic LDS: L*C elements + L twiddles
-// + L row flags.
-// One workgroup's share of a first/middle pass: logical block blk of grid g.
-// smem: L*C elements + L twiddles + L row flags.
+// the outer index and k transposed.  One workgroup's share of the pass is the
+// logical block blk.  smem: L*C elements + L twiddles + L row flags.  C is a
+// power of two that divides NT, so a thread keeps one column c = tid mod C
+// and visits rows l0, l0 + NT/C, ... (l0 = tid / C): its global addresses are
+// a base plus uniform strides.
 template <typename Real, int EMAX, int NT>
 __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
                                typename cplx<Real>::T* out, const unsigned char* rflag,
@@ -250,72 +251,61 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
   T2* twL = buf + L * C;
   unsigned char* rf = reinterpret_cast<unsigned char*>(twL + L);
   const int64_t S = ps.S, P = ps.P;
-  const int64_t nsb = (S + C - 1) / C;
-  const int64_t pidx = blk / nsb;
-  const int64_t s0 = (blk - pidx * nsb) * C;
+  const uint32_t nsb = (uint32_t)((S + C - 1) / C);
+  const uint32_t pidx32 = (uint32_t)blk / nsb;
+  const int64_t pidx = pidx32;
+  const int64_t s0 = (int64_t)((uint32_t)blk - pidx32 * nsb) * C;
   const int ceff = (int)((S - s0) < C ? (S - s0) : C);
   for (int x = tid; x < L; x += NT) {
     twL[x] = tw[ps.twL_off + x];
     rf[x] = rflag ? rflag[x] : (unsigned char)1;
   }
+  const int c = tid & (C - 1);
+  const int l0 = tid >> csh;
+  const int LS = NT >> csh;  // rows between a thread's consecutive elements
+  const bool cok = c < ceff;
   __syncthreads();
-  const int E = L * C;
-  const int64_t inbase = pidx * (int64_t)L * S + s0;
   constexpr int PER = (EMAX + NT - 1) / NT;
+  const T2* pin = in + pidx * (int64_t)L * S + s0 + (int64_t)l0 * S + c;
+  const int64_t istep = (int64_t)LS * S;
   T2 v[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
+    const int l = l0 + i * LS;
     v[i] = czero<T2>();
-    if (e < E) {
-      const int l = e >> csh;
-      const int c = e & (C - 1);
-      if (c < ceff && rf[l]) v[i] = in[inbase + (int64_t)l * S + c];
-    }
+    if (l < L && cok && rf[l]) v[i] = pin[i * istep];
   }
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    if (e < E) buf[e] = v[i];
-  }
-  // Inter-pass twiddles exp(2 pi i s k / N) of this thread's outputs,
-  // started before the transform so that their latency overlaps it.  The
-  // thread's outputs share the column s and their k steps by NT/C, so all of
-  // them follow from two table values (first k, step) by multiplication.
+  for (int i = 0; i < PER; ++i)
+    if (l0 + i * LS < L) buf[tid + i * NT] = v[i];
+  // Inter-pass twiddles exp(2 pi i s k / N), N = L S, of this thread's
+  // outputs (column s = s0 + c, rows k = l0 + i LS), fetched before the
+  // transform so that their latency overlaps it: the first from the table,
+  // the others by repeated multiplication with the step exp(2 pi i s LS / N).
+  // Threads without outputs (l0 >= L or c >= ceff) and threads with a single
+  // output (LS >= L) take index 0 for what they do not use, so every index is
+  // below N.
   const int64_t mask = ((int64_t)1 << ps.bshift) - 1;
   const T2* tlo = tw + ps.twlo_off;
   const T2* thi = tw + ps.twhi_off;
-  const int64_t Ntw = (int64_t)L * S;
-  const int64_t scol = s0 + (tid & (C - 1));
-  const int64_t q0 = (scol * (int64_t)(tid >> csh)) % Ntw;  // rows past L are unused
-  const int64_t qs = (scol * (int64_t)(NT >> csh)) % Ntw;
+  const int64_t scol = s0 + c;
+  const int64_t q0 = (cok && l0 < L) ? scol * (int64_t)l0 : 0;
+  const int64_t qs = (cok && LS < L) ? scol * (int64_t)LS : 0;
   const T2 w0 = cmul(thi[q0 >> ps.bshift], tlo[q0 & mask]);
   const T2 ws = cmul(thi[qs >> ps.bshift], tlo[qs & mask]);
   __syncthreads();
-  lds_fft<EMAX, NT>(buf, L, C, 1, C, ps.rad, ps.nrad, twL, false);
+  lds_fft<EMAX, NT>(buf, L, C, C, ps.rad, ps.nrad, twL);
   const int64_t PS = P * S;
+  T2* pout = out + (int64_t)l0 * PS + pidx * S + s0 + c;
+  const int64_t ostep = (int64_t)LS * PS;
   T2 tk = w0;
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
-    const int e = tid + i * NT;
-    if (e < E) {
-      const int k = e >> csh;
-      const int c = e & (C - 1);
-      if (c < ceff) {
-        const int64_t s = s0 + c;
-        out[(int64_t)k * PS + pidx * S + s] = cmul(buf[e], tk);
-      }
-    }
+    if (l0 + i * LS < L && cok) pout[i * ostep] = cmul(buf[tid + i * NT], tk);
     tk = cmul(tk, ws);
   }
   __syncthreads();
 }
-
-// A first/middle pass: workgroup = C consecutive columns s of one outer index
-// p; loads L x C elements (C contiguous per row, 128-256 B segments),
-// transforms along L in LDS, applies the inter-pass twiddle and stores with
-// the outer index and k transposed.  Dynamic LDS: L*C elements + L twiddles
-// + L row flags.
 
 // Power of the floating-mean Lomb-Scargle fit from the three normalised sums
 // A = sum w^ y~ e^{iwt}, B = sum w^ e^{iwt}, B2 = sum w^ e^{2iwt}
@@ -354,10 +344,15 @@ __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, doub
 // Last pass: D rows of length L per workgroup for the G grids, transformed in
 // LDS; output k of row p is the mode m = p + P k.  Deconvolution, crop to the
 // nf requested modes and (G = 3) the power are fused into the store.
-// Dynamic LDS: G*D*(L+1) elements + L twiddles.
 // One workgroup's share of the last pass: D rows starting at p0 = blk*D.
-// smem: G*D*(L+1) elements + L twiddles.  nf and K are those of the series
-// (a batched series may use fewer frequencies than its grid's plan).
+// The G*D rows are interleaved in LDS, element l of row r at l*R + r with
+// R = G*D: every wave access of a stage (and of the power readout) is then a
+// run of consecutive elements, which the LDS serves without bank conflicts.
+// The global loads take the row index fastest (lanes (l, d), D rows of one
+// grid), so that their LDS stores are contiguous runs too while each row is
+// still read in contiguous 16-element pieces.  smem: L*R elements + L
+// twiddles.  nf and K are those of the series (a batched series may use fewer
+// frequencies than its grid's plan).
 template <typename Real, int G, int EMAX, int NT>
 __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPass& ps,
                                int64_t n, int64_t nf, int64_t K, const CallArgs& a,
@@ -367,33 +362,33 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
   const int L = ps.L, D = ps.C;
-  const int Lp = L + 1;
+  const int R = G * D;
   T2* buf = reinterpret_cast<T2*>(smem);
-  T2* twL = buf + G * D * Lp;
+  T2* twL = buf + L * R;
   const int64_t P = ps.P;
   const int64_t p0 = blk * D;
   const int deff = (int)((P - p0) < D ? (P - p0) : D);
   for (int x = tid; x < L; x += NT) twL[x] = tw[ps.twL_off + x];
   const int E = D * L;
+  const int dsh = __builtin_ctz(D);  // D is a power of two
   constexpr int PER = (EMAX / G + NT - 1) / NT;
+  // element e = l D + d of the block's rows (row d, position l)
+  const int d0 = tid & (D - 1);
+  const int l0 = tid >> dsh;
+  const int LS = NT >> dsh;  // NT is a multiple of D
 #pragma unroll
   for (int g = 0; g < G; ++g) {
-    const T2* in = b.in[g] + p0 * (int64_t)L;
+    const T2* in = b.in[g] + (p0 + d0) * (int64_t)L + l0;
     T2 v[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
       v[i] = czero<T2>();
-      if (e < E && e < deff * L) v[i] = in[e];
+      if (l0 + i * LS < L && d0 < deff) v[i] = in[i * LS];
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = tid + i * NT;
-      if (e < E) {
-        const int d = e / L;
-        const int l = e - d * L;
-        buf[(g * D + d) * Lp + l] = v[i];
-      }
+      const int l = l0 + i * LS;
+      if (l < L) buf[__mul24(l, R) + g * D + d0] = v[i];
     }
   }
   __syncthreads();
@@ -405,8 +400,8 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
 #pragma unroll
   for (int i = 0; i < PO; ++i) {
     const int e = tid + i * NT;
-    const int d = e % D;
-    const int k = e / D;
+    const int d = e & (D - 1);
+    const int k = e >> dsh;
     kov[i] = -1;
     ipv[i] = 0.0;
     if (e < E && d < deff) {
@@ -419,19 +414,19 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       }
     }
   }
-  lds_fft<EMAX, NT>(buf, L, G * D, Lp, 1, ps.rad, ps.nrad, twL, true);
+  lds_fft<EMAX, NT>(buf, L, G * D, R, ps.rad, ps.nrad, twL);
 #pragma unroll
   for (int i = 0; i < PO; ++i) {
     const int64_t kout = kov[i];
     if (kout < 0) continue;
     const int e = tid + i * NT;
-    const int d = e % D;
-    const int k = e / D;
+    const int d = e & (D - 1);
+    const int k = e >> dsh;
     const double ip = ipv[i];
     if (G == 3) {
-      const T2 A = buf[(0 * D + d) * Lp + k];
-      const T2 B = buf[(1 * D + d) * Lp + k];
-      const T2 B2 = buf[(2 * D + d) * Lp + k];
+      const T2 A = buf[k * R + d];
+      const T2 B = buf[k * R + D + d];
+      const T2 B2 = buf[k * R + 2 * D + d];
       double s6[6] = {(double)A.x * ip,  (double)A.y * ip,  (double)B.x * ip,
                       (double)B.y * ip,  (double)B2.x * ip, (double)B2.y * ip};
       const int64_t q = kout - st.k_lo;
@@ -441,18 +436,13 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       if (kout == a.kzero) pw = 0.0;
       a.power[kout] = pw;
     } else {
-      const T2 A = buf[d * Lp + k];
+      const T2 A = buf[k * R + d];
       double2 v = make_double2((double)A.x * ip, (double)A.y * ip);
       reinterpret_cast<double2*>(a.sums)[kout] = v;
     }
   }
   __syncthreads();
 }
-
-// Last pass: D rows of length L per workgroup for the G grids, transformed in
-// LDS; output k of row p is the mode m = p + P k.  Deconvolution, crop to the
-// nf requested modes and (G = 3) the power are fused into the store.
-// Dynamic LDS: G*D*(L+1) elements + L twiddles.
 
 // ---------------------------------------------------------------------------
 // Direct sums near f = 0.

@@ -20,6 +20,14 @@ namespace {
 constexpr int kTileMaxCells = kTileMax;  // spreading tile (LDS accumulator)
 constexpr int kMaxWidth = 20;            // widest spreading kernel
 constexpr int kLmaxPass = kLmax;         // longest per-pass FFT length
+constexpr size_t kLdsMax = 65536;        // dynamic LDS of one workgroup
+
+// LDS of the last pass for d rows of length L of G grids (interleaved rows at
+// pitch last_pitch(G d), plus L twiddles) fits one workgroup.
+static bool last_lds_ok(int G, int d, int L, int prec) {
+  const size_t elem = prec == 1 ? 8 : 16;
+  return elem * ((size_t)L * (size_t)last_pitch(G * d) + (size_t)L) <= kLdsMax;
+}
 
 std::vector<int64_t> smooth_in_range(int64_t lo, int64_t hi) {
   std::vector<int64_t> v;
@@ -171,7 +179,7 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
       std::vector<int> lens;
       bool ok = false;
       if (np == 1) {
-        if (G * (n + 1) <= elast && n <= kLmaxPass) {
+        if (G * (n + 1) <= elast && n <= kLmaxPass && last_lds_ok(G, 1, (int)n, r.prec)) {
           lens.push_back((int)n);
           ok = true;
         }
@@ -179,7 +187,7 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
         // last length: largest with >= dmin rows per workgroup
         const int llast_max = std::min<int64_t>(elast / (G * dmin) - 1, kLmaxPass);
         for (int Ll = llast_max; Ll >= 2 && !ok; --Ll) {
-          if (n % Ll || !is_smooth(Ll)) continue;
+          if (n % Ll || !is_smooth(Ll) || !last_lds_ok(G, dmin, Ll, r.prec)) continue;
           std::vector<int> mids;
           if (split_mid(n / Ll, np - 1, std::min(kLmaxPass, emid / 4), &mids)) {
             lens = mids;
@@ -228,8 +236,10 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
       while ((1 << ps.cshift) < c) ++ps.cshift;
     } else {
       int d = 1;
-      while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P) d *= 2;
-      if (G * d * (ps.L + 1) > elast) {
+      while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P &&
+             last_lds_ok(G, 2 * d, ps.L, r.prec))
+        d *= 2;
+      if (G * d * (ps.L + 1) > elast || !last_lds_ok(G, d, ps.L, r.prec)) {
         if (err) *err = "last FFT pass does not fit one workgroup";
         return false;
       }

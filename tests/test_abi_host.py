@@ -3,6 +3,8 @@ symbol of include/mils.h, argument validation returns the documented codes,
 and the planner's choices satisfy their invariants."""
 import ctypes
 import math
+
+import numpy as np
 import os
 import re
 
@@ -124,6 +126,18 @@ def test_planner_invariants(nf, eps, prec):
     margin = 8 if prec == "fp64" else 2
     assert math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])) <= eps / margin * 1.0001
     assert n % d["tile"] == 0 and d["tile"] <= 1024
+    assert 1 <= d["last_rows"] <= 8 and 0 < d["last_lds_bytes"] <= 65536
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_last_pass_fits_one_workgroup_over_a_size_sweep(prec):
+    # the last pass keeps L * pitch + L elements in LDS (pitch = 3 rows)
+    for nf in sorted({int(x) for x in np.geomspace(1, 3e7, 300)}):
+        d = mils.plan_info(nd=1000, nf=nf, eps=1e-9 if prec == "fp64" else 1e-5, precision=prec)
+        L, D = d["len"][-1], d["last_rows"]
+        elem = 16 if prec == "fp64" else 8
+        assert d["last_lds_bytes"] == elem * (L * 3 * D + L) <= 65536, (nf, d)
+        assert 3 * D * L <= (3072 if prec == "fp64" else 6144), (nf, d)
 
 
 def test_kernel_error_estimate_falls_with_tolerance():
