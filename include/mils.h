@@ -126,6 +126,18 @@ int mils_context_destroy(mils_context *ctx);
  * Host-only; valid on a host-only context. */
 int mils_plan_info(mils_context *ctx, int64_t nd, const mils_params *p, mils_plan_desc *out);
 
+/* The polynomial table the spreading kernel is evaluated from, for the plan of
+ * a periodogram with parameters p (host-only; valid on a host-only context).
+ * The kernel is the exponential of semicircle phi(z) = exp(beta (sqrt(1 - z^2)
+ * - 1)) (Sec. 2 of the paper); at the w cells of a point whose first covered
+ * cell lies t in [0, 1) cells past the left end of its support, cell k takes
+ * phi((k + t) / (w/2) - 1) ~= sum_j coef[j * kmax + k] u^(ncoef - 1 - j),
+ * u = 2t - 1.  coef receives ncoef * kmax doubles (caller-owned, at least
+ * 15 * 20); *ncoef, *kmax, *width and *beta describe it.  The device uses
+ * the same values (rounded to FP32 for the FP32 precision form). */
+int mils_kernel_table(mils_context *ctx, const mils_params *p, double *coef, int32_t *ncoef,
+                      int32_t *kmax, int32_t *width, double *beta);
+
 /* Check the arguments of mils_periodogram without touching the device;
  * returns MILS_OK or the code mils_periodogram would return before launching. */
 int mils_check_periodogram_args(const double *t, const double *y, int64_t nd,

@@ -179,11 +179,14 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
     std::vector<double> z, gphi;
     phihat_nodes(e.plan, &z, &gphi);
     const size_t nbytes = sizeof(double) * 2 * z.size();
-    e.bytes = twbytes + phbytes + nbytes;
+    std::vector<double> hc;
+    make_horner(e.plan, &hc);
+    const size_t hbytes = hc.size() * (prec == 1 ? sizeof(float) : sizeof(double));
+    e.bytes = twbytes + phbytes + nbytes + hbytes;
     if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + e.bytes > ctx->budget)
       return fail(ctx, MILS_ERR_OOM, "plan tables exceed the HBM budget");
     char* buf = nullptr;
-    hipError_t he = hipMalloc(&buf, twbytes + phbytes + nbytes + 512);
+    hipError_t he = hipMalloc(&buf, twbytes + phbytes + nbytes + hbytes + 1024);
     if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "hipMalloc of plan tables failed");
     e.inv_phihat = reinterpret_cast<double*>(buf);
     e.tw = buf + ((phbytes + 255) & ~(size_t)255);
@@ -200,6 +203,15 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
     zn.insert(zn.end(), gphi.begin(), gphi.end());
     he = hipMemcpy(nodes, zn.data(), nbytes, hipMemcpyHostToDevice);
     if (he != hipSuccess) return hip_fail(ctx, he, "plan upload");
+    char* hdev = reinterpret_cast<char*>(nodes) + ((nbytes + 255) & ~(size_t)255);
+    if (prec == 1) {
+      std::vector<float> f(hc.begin(), hc.end());
+      he = hipMemcpy(hdev, f.data(), hbytes, hipMemcpyHostToDevice);
+    } else {
+      he = hipMemcpy(hdev, hc.data(), hbytes, hipMemcpyHostToDevice);
+    }
+    if (he != hipSuccess) return hip_fail(ctx, he, "plan upload");
+    e.plan.hcoef = hdev;
     he = launch_phihat(e.inv_phihat, e.plan.K, (double)e.plan.w, (double)e.plan.n, nodes,
                        nodes + z.size(), (int)z.size(), nullptr);
     if (he == hipSuccess) he = hipDeviceSynchronize();
@@ -436,6 +448,24 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
     out->last_lds_bytes = (int32_t)((pl.prec == 1 ? 8 : 16) *
                                     ((size_t)lp.L * last_pitch(3 * lp.C) + lp.L));
   }
+  return MILS_OK;
+}
+
+int mils_kernel_table(mils_context* ctx, const mils_params* p, double* coef, int32_t* ncoef,
+                      int32_t* kmax, int32_t* width, double* beta) {
+  if (!ctx || !coef || !ncoef || !kmax || !width || !beta) return MILS_ERR_INVALID_ARG;
+  int rc = check_params(p);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid plan query");
+  PlanEntry* pe = nullptr;
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false);
+  if (rc != MILS_OK) return rc;
+  std::vector<double> hc;
+  make_horner(pe->plan, &hc);
+  std::copy(hc.begin(), hc.end(), coef);
+  *ncoef = horner_n(pe->plan.prec);
+  *kmax = kHornerK;
+  *width = pe->plan.w;
+  *beta = pe->plan.beta;
   return MILS_OK;
 }
 

@@ -269,26 +269,65 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
 }
 
 // ============================================================================
-// Spreading.  One workgroup per tile of T consecutive cells of one row of the
-// [nrows][S1] view of the grid.  It gathers every point whose kernel support
+// Spreading.  A tile is T consecutive cells of one row of the [nrows][S1]
+// view of the grid; its workgroup gathers every point whose kernel support
 // (w cells around u) meets the tile, accumulates the kernel-weighted
 // strengths in LDS and writes the tile once: no global atomics, no halo
 // exchange, and the result does not depend on how tiles are scheduled.
-// Rows that no kernel support reaches are not written; their flag tells the
-// first FFT pass to treat them as zero.
+// Rows that no kernel support reaches are not written (nor visited); their
+// flag tells the first FFT pass to treat them as zero.
 // ============================================================================
+// Row classification for the spread: the flag of every row of geometry GEO
+// (1 if a kernel support reaches it) and the list of active rows in order.
+// One workgroup of kRowThreads threads; nrows <= kRowThreads (nrows is the
+// first FFT length, at most kLmax).
+constexpr int kRowThreads = 1024;
+static_assert(kLmax <= kRowThreads, "one thread per row");
+template <int GEO>
+__global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int nd,
+                                                           unsigned char* rowflag, int* act_rows,
+                                                           int slot) {
+  __shared__ int scan[kRowThreads];
+  const DevStats* st = w.stats;
+  if (st->status != 0) return;
+  const int r = threadIdx.x;
+  const int h = (int)ceil(p.hw) + 1;
+  int active = 0;
+  if (r < p.nrows) {
+    active = row_active<GEO>(r, h, p, w.bin_start, nd);
+    rowflag[r] = (unsigned char)active;
+  }
+  scan[r] = active;
+  __syncthreads();
+  for (int off = 1; off < kRowThreads; off <<= 1) {
+    const int x = r >= off ? scan[r - off] : 0;
+    __syncthreads();
+    scan[r] += x;
+    __syncthreads();
+  }
+  if (active) act_rows[scan[r] - 1] = r;
+  if (r == kRowThreads - 1) w.nact[slot] = scan[r];
+}
+
+// Spreading over the tiles of the active rows only (their list and count come
+// from k_row_class): a fixed grid of workgroups takes tiles blk, blk + grid,
+// ...; every tile is written by exactly one workgroup, so the result does not
+// depend on scheduling.  T divides the row length S1 here.
 template <typename Real, int GEO, int NG>
-__global__ __launch_bounds__(kThreads) void k_spread(CallArgs a, Plan p, Work w, int gbase,
-                                                     unsigned char* rowflag) {
+__global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Work w, int gbase,
+                                                          const int* act_rows, int slot) {
   __shared__ Real acc[NG * 2 * kTileMax];
   __shared__ int rb[8], re[8], sv[2];
   const DevStats* stp = w.stats;
   if (stp->status != 0) return;
-  // tiles in launch order: consecutive tiles land on different XCDs, which
-  // spreads the active rows (a contiguous fraction of the grid) over the chip
-  const int tile = blockIdx.x;
-  spread_tile<Real, GEO, NG, kThreads>(tile, p.T, kTileMax, a, p, w, *stp, gbase, rowflag, acc, rb,
-                                       re, sv);
+  const int tpr = (int)(p.S1 / p.T);
+  const int ntile = w.nact[slot] * tpr;
+  for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const int q = t / tpr;
+    const int tile = act_rows[q] * tpr + (t - q * tpr);
+    spread_tile<Real, GEO, NG, kThreads, true>(tile, p.T, kTileMax, a, p, w, *stp, gbase, nullptr,
+                                               acc, rb, re, sv);
+  }
 }
 
 // ============================================================================
@@ -450,20 +489,25 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   mark(kStageBin, 0);
 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
+  const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
+  const int nd = (int)a.nd;
+  mark(kStageSpreadF, 1);
+  hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
+                     w.act_rows_f, 0);
+  if (a.periodogram)
+    hipLaunchKernelGGL((k_spread_rows<Real, 1, 2>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
+                       w.act_rows_f, 0);
+  else
+    hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
+                       w.act_rows_f, 0);
+  mark(kStageSpreadF, 0);
   if (a.periodogram) {
-    mark(kStageSpreadF, 1);
-    hipLaunchKernelGGL((k_spread<Real, 1, 2>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a, p,
-                       w, 0, w.rowflag_f);
-    mark(kStageSpreadF, 0);
     mark(kStageSpread2F, 1);
-    hipLaunchKernelGGL((k_spread<Real, 2, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a, p,
-                       w, 2, w.rowflag_2f);
+    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
+                       w.act_rows_2f, 1);
+    hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 2,
+                       w.act_rows_2f, 1);
     mark(kStageSpread2F, 0);
-  } else {
-    mark(kStageSpreadF, 1);
-    hipLaunchKernelGGL((k_spread<Real, 1, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, s, a, p,
-                       w, 0, w.rowflag_f);
-    mark(kStageSpreadF, 0);
   }
   const T2* tw = reinterpret_cast<const T2*>(w.tw);
   // passes 0 .. npass-2

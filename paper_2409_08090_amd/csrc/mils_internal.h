@@ -50,7 +50,16 @@ struct Plan {
   int64_t nbins;           // ceil(n / Tb)
   int D;                   // rows per workgroup of the last pass
   int64_t tw_count;        // complex entries in the twiddle buffer
+  const void* hcoef;       // device: kernel polynomial coefficients (Real), see kHornerK
 };
+
+// The spreading kernel at the w cells of a point is evaluated as w
+// polynomials in u = 2t - 1, t = the point's offset from its first cell
+// (plan-owned table of kHornerN(prec) x kHornerK Reals, highest degree first,
+// zero rows for k >= w).
+constexpr int kHornerK = 20;                  // widest kernel (cells)
+constexpr int kHornerN64 = 15, kHornerN32 = 9;  // coefficients per polynomial
+__host__ __device__ constexpr inline int horner_n(int prec) { return prec == 1 ? kHornerN32 : kHornerN64; }
 
 // Scalars produced on the device by the statistics kernel.
 struct DevStats {
@@ -102,6 +111,9 @@ struct Work {
   double* hs;
   unsigned char* rowflag_f;   // nrows
   unsigned char* rowflag_2f;  // nrows
+  int* act_rows_f;            // nrows: active rows of geometry f, in order
+  int* act_rows_2f;           // nrows: same for geometry 2f
+  int* nact;                  // 2: number of active rows (f, 2f)
   void* grid[3];          // G grids of n complex
   void* grid2[3];         // second buffers for passes >= 2
   const void* tw;         // twiddles (plan-owned)
@@ -114,6 +126,7 @@ constexpr int kStatsBlocks = 1024;
 constexpr int kThreads = 256;       // threads of most kernels
 constexpr int kThreadsLast = 512;   // threads of the last FFT pass
 constexpr int kTileMax = 1024;      // spreading tile (cells)
+constexpr int kSpreadGrid = 2048;   // workgroups of the persistent spread
 constexpr int kLmax = 1024;         // longest per-pass FFT length
 // elements held in LDS by one workgroup of a first/middle pass and of the last pass
 constexpr int kEmid64 = 2048, kEmid32 = 4096;

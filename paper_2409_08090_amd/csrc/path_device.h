@@ -88,13 +88,62 @@ __device__ __forceinline__ int gather_ranges(int* rb, int* re, int64_t c0, int64
   return cnt;
 }
 
+// The plan's kernel table is read-only for the whole launch: reading it
+// through the constant address space lets the compiler use scalar loads (one
+// per wave, not per lane) and feed the coefficients to the FMAs from SGPRs.
+template <typename Real>
+using ConstPtr = const __attribute__((address_space(4))) Real*;
+
+// The w kernel values of a point (plan table hc, see kHornerK): each
+// polynomial as a sum of coefficient x power of u, the powers formed once per
+// point, so that every term is one multiply-add with the coefficient taken
+// straight from a scalar register (|u| <= 1 and the coefficients are below
+// one in magnitude: as accurate as Horner's rule).  Groups of four cells past
+// the width are skipped.
+template <typename Real>
+__device__ __forceinline__ void horner_kernel(ConstPtr<Real> hc, Real u, int wd, Real* ker) {
+  constexpr int NC = sizeof(Real) == 8 ? kHornerN64 : kHornerN32;
+  Real pw[NC];
+  pw[0] = (Real)1;
+  pw[1] = u;
+#pragma unroll
+  for (int i = 2; i < NC; ++i) pw[i] = pw[i / 2] * pw[i - i / 2];
+#pragma unroll
+  for (int k0 = 0; k0 < kHornerK; k0 += 4) {
+    if (k0 < wd) {
+#pragma unroll
+      for (int k = k0; k < k0 + 4; ++k) ker[k] = hc[(NC - 1) * kHornerK + k];
+#pragma unroll
+      for (int i = 1; i < NC; ++i)
+#pragma unroll
+        for (int k = k0; k < k0 + 4; ++k) ker[k] += hc[(NC - 1 - i) * kHornerK + k] * pw[i];
+    } else {
+#pragma unroll
+      for (int k = k0; k < k0 + 4; ++k) ker[k] = 0;
+    }
+  }
+}
+
+// Whether any kernel support of geometry GEO reaches row r of the
+// [nrows][S1] view of the grid (h: half-width in cells, rounded up, plus one).
+template <int GEO>
+__device__ __forceinline__ bool row_active(int64_t r, int h, const Plan& p, const int* bs, int nd) {
+  int rb[4], re[4];
+  const int cnt = gather_ranges<GEO>(rb, re, r * p.S1 - h, (r + 1) * p.S1 + h, p, bs, nd);
+  int tot = 0;
+  for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
+  return tot > 0;
+}
+
 // Spread one tile of geometry GEO into NG grids: cells [tile*T, tile*T + T)
 // of the flat grid, where T either divides the row length S1 of the
-// [nrows][S1] view or is a whole number of rows.  The flag of every row that
-// starts inside the tile is written.  acc: LDS accumulator of NG*2*tcap Reals
-// (T <= tcap); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by every
-// thread of the workgroup (it contains barriers).
-template <typename Real, int GEO, int NG, int NT>
+// [nrows][S1] view or is a whole number of rows.  Unless KNOWN (the caller
+// already knows that the tile lies in an active row and has written the row
+// flags), the flag of every row that starts inside the tile is written and a
+// tile of inactive rows returns at once.  acc: LDS accumulator of NG*2*tcap
+// Reals (T <= tcap); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by
+// every thread of the workgroup (it contains barriers).
+template <typename Real, int GEO, int NG, int NT, bool KNOWN = false>
 __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const Plan& p,
                             const Work& w, const DevStats& st, int gbase, unsigned char* rowflag,
                             Real* acc, int* rb, int* re, int* sv) {
@@ -105,7 +154,12 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
   const int h = (int)ceil(p.hw) + 1;
   const int nd = (int)a.nd;
   const int* bs = w.bin_start;
-  if (tid == 0) {
+  if (KNOWN) {
+    if (tid == 0) {
+      sv[1] = 1;
+      sv[0] = gather_ranges<GEO>(rb, re, a0 - h, a0 + T + h, p, bs, nd);
+    }
+  } else if (tid == 0) {
     const int64_t r0 = a0 / p.S1, r1 = (a0 + T - 1) / p.S1;
     int any = 0;
     for (int64_t r = r0; r <= r1; ++r) {
@@ -144,8 +198,7 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
   const double nreal = (double)p.n;
   const int wd = p.w;
   const double hw = p.hw;
-  const double inv_hw = 1.0 / p.hw;
-  const Real beta = (Real)p.beta;
+  const ConstPtr<Real> hc = (ConstPtr<Real>)(p.hcoef);
   // a kernel support can meet the tile at most once unless the tile spans
   // nearly the whole periodic grid
   const bool wrap_free = T <= n - wd;
@@ -194,17 +247,23 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
         hre[0] = (Real)(hv * pc);
         him[0] = (Real)(hv * ps);
       }
-      for (int k = 0; k < wd; ++k) {
-        int loc = lb + k;
-        if (loc < 0) loc += n;
-        else if (loc >= n) loc -= n;
-        if (loc >= T) continue;
-        const Real z = (Real)(((double)(o0 + k) - frac) * inv_hw);
-        const Real v = es_kernel(z, beta);
+      // kernel values at cells cell + o0 + k: polynomials in u = 2t - 1 with
+      // t = o0 + hw - frac in [0, 1)
+      Real ker[kHornerK];
+      horner_kernel<Real>(hc, (Real)(2.0 * ((double)o0 + hw - frac) - 1.0), wd, ker);
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
-          atomicAdd(&acc[(2 * g) * tcap + loc], v * hre[g]);
-          atomicAdd(&acc[(2 * g + 1) * tcap + loc], v * him[g]);
+      for (int k = 0; k < kHornerK; ++k) {
+        if (k < wd) {
+          int loc = lb + k;
+          if (loc < 0) loc += n;
+          else if (loc >= n) loc -= n;
+          if (loc < T) {
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              atomicAdd(&acc[(2 * g) * tcap + loc], ker[k] * hre[g]);
+              atomicAdd(&acc[(2 * g + 1) * tcap + loc], ker[k] * him[g]);
+            }
+          }
         }
       }
     }

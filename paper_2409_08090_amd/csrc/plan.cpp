@@ -362,6 +362,9 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
   x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax));
   x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));
+  x.act_rows_f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
+  x.act_rows_2f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
+  x.nact = reinterpret_cast<int*>(take(sizeof(int) * 2));
   const size_t cbytes = p.prec == 1 ? 8 : 16;
   for (int g = 0; g < G; ++g) x.grid[g] = take(cbytes * p.n);
   if (p.npass >= 3)
@@ -369,6 +372,43 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
   off = (off + 255) & ~(size_t)255;
   if (w) *w = x;
   return off;
+}
+
+void make_horner(const Plan& p, std::vector<double>* coef) {
+  const int N = horner_n(p.prec);
+  const long double pi = 3.14159265358979323846264338327950288L;
+  const long double hw = 0.5L * (long double)p.w;
+  const long double beta = (long double)p.beta;
+  coef->assign((size_t)N * kHornerK, 0.0);
+  std::vector<long double> fv(N), ch(N), mono(N), tm1(N), t0(N), t1(N);
+  for (int k = 0; k < p.w && k < kHornerK; ++k) {
+    // samples at the Chebyshev points u_i of [-1, 1] (t = (u + 1) / 2)
+    for (int i = 0; i < N; ++i) {
+      const long double u = cosl(pi * (2 * i + 1) / (2.0L * N));
+      const long double z = ((long double)k + 0.5L * (u + 1.0L)) / hw - 1.0L;
+      const long double a = 1.0L - z * z;
+      fv[i] = a >= 0 ? expl(beta * (sqrtl(a) - 1.0L)) : 0.0L;
+    }
+    for (int m = 0; m < N; ++m) {
+      long double acc = 0;
+      for (int i = 0; i < N; ++i) acc += fv[i] * cosl(pi * m * (2 * i + 1) / (2.0L * N));
+      ch[m] = (m == 0 ? 1.0L : 2.0L) * acc / N;
+    }
+    // sum_m ch[m] T_m(u) as a polynomial in u (T_1 = u, T_{m+1} = 2u T_m - T_{m-1})
+    std::fill(mono.begin(), mono.end(), 0.0L);
+    std::fill(tm1.begin(), tm1.end(), 0.0L);
+    std::fill(t0.begin(), t0.end(), 0.0L);
+    t0[0] = 1.0L;  // T_0
+    for (int m = 0; m < N; ++m) {
+      for (int j = 0; j < N; ++j) mono[j] += ch[m] * t0[j];
+      // t1 = T_{m+1}: u T_0 for m = 0, else 2 u T_m - T_{m-1}
+      const long double two = m == 0 ? 1.0L : 2.0L;
+      for (int j = 0; j < N; ++j) t1[j] = -tm1[j] + (j > 0 ? two * t0[j - 1] : 0.0L);
+      tm1 = t0;
+      t0 = t1;
+    }
+    for (int j = 0; j < N; ++j) (*coef)[(size_t)(N - 1 - j) * kHornerK + k] = (double)mono[j];
+  }
 }
 
 }  // namespace mils

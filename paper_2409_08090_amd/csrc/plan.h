@@ -43,6 +43,11 @@ void make_twiddles(Plan* p, std::vector<double>* tw);
 // the phihat kernel (even rule of q points on [-1, 1], positive half).
 void phihat_nodes(const Plan& p, std::vector<double>* z, std::vector<double>* gphi);
 
+// Monomial coefficients of the kernel polynomials (Chebyshev interpolation of
+// phi((k + t)/hw - 1), t in [0, 1], in long double): coef[j * kHornerK + k],
+// j = 0 the highest degree, horner_n(p.prec) coefficients, k < kHornerK.
+void make_horner(const Plan& p, std::vector<double>* coef);
+
 // Device workspace layout of one call; returns the byte size.  With base ==
 // nullptr only the size is computed.
 size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w);

@@ -12,7 +12,8 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmils.so")
+# the in-tree build, unless MILS_LIB names another build of the same library
+LIB_PATH = os.environ.get("MILS_LIB") or os.path.join(HERE, "libmils.so")
 
 MILS_OK = 0
 MILS_ERR_INVALID_ARG = -1
@@ -91,6 +92,9 @@ SIGNATURES = {
     "mils_context_destroy": ([_P], ctypes.c_int),
     "mils_plan_info": ([_P, ctypes.c_int64, ctypes.POINTER(mils_params),
                         ctypes.POINTER(mils_plan_desc)], ctypes.c_int),
+    "mils_kernel_table": ([_P, ctypes.POINTER(mils_params), _P, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "mils_check_periodogram_args": ([_P, _P, ctypes.c_int64, ctypes.POINTER(mils_params), _P],
                                     ctypes.c_int),
     "mils_trig_sums": ([_P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
@@ -213,6 +217,21 @@ def make_params(f0, df, nf, eps=1e-9, precision="fp64", normalization="standard"
     flags = (MILS_CENTER_DATA if center_data else 0) | (MILS_FIT_MEAN if fit_mean else 0)
     return mils_params(float(f0), float(df), int(nf), float(eps), PRECISIONS[precision],
                        NORMALIZATIONS[normalization], flags)
+
+
+def kernel_table(nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01):
+    """(coef[ncoef, kmax], width, beta) of the spreading-kernel polynomials of a
+    plan (host only, no GPU needed)."""
+    import numpy as np
+    lib = load()
+    ctx = Context(-1)
+    p = make_params(f0, df, nf, eps, precision)
+    buf = np.zeros(64 * 64, dtype=np.float64)
+    nc, km, wd, be = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    ctx.check(lib.mils_kernel_table(ctx.handle, ctypes.byref(p), buf.ctypes.data, ctypes.byref(nc),
+                                    ctypes.byref(km), ctypes.byref(wd), ctypes.byref(be)))
+    ctx.close()
+    return buf[: nc.value * km.value].reshape(nc.value, km.value).copy(), wd.value, be.value
 
 
 def plan_info(nd, nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01) -> dict:

@@ -165,3 +165,29 @@ def test_server_config_and_device_checks():
     assert lib.mils_server_create(0, None, None) == mils.MILS_ERR_INVALID_ARG
     assert lib.mils_server_submit(None, None, None) == mils.MILS_ERR_INVALID_ARG
     assert lib.mils_server_destroy(None) == mils.MILS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nf,eps,prec", [(12_000_000, 1e-9, "fp64"), (100_000, 1e-12, "fp64"),
+                                         (100_000, 1e-6, "fp64"), (1000, 1e-9, "fp64"),
+                                         (12_000_000, 1e-5, "fp32"), (5000, 1e-3, "fp32")])
+def test_kernel_polynomials_reproduce_the_es_kernel(nf, eps, prec):
+    # The spread evaluates phi(z) = exp(beta (sqrt(1 - z^2) - 1)) at the w cells of
+    # a point from per-cell polynomials; here they are checked against phi itself.
+    coef, w, beta = mils.kernel_table(nf, eps, prec)
+    nc, kmax = coef.shape
+    assert kmax >= w and not np.any(coef[:, w:])
+    t = np.linspace(0.0, 1.0, 1001, endpoint=False)
+    u = 2 * t - 1
+    worst = 0.0
+    for k in range(w):
+        acc = np.zeros_like(u)
+        for j in range(nc):
+            acc = acc * u + coef[j, k]
+        z = (k + t) / (w / 2) - 1
+        ref = np.exp(beta * (np.sqrt(np.maximum(1 - z * z, 0.0)) - 1))
+        worst = max(worst, np.max(np.abs(acc - ref)))
+    # limited by the kink of phi at |z| = 1, of size exp(-beta), and by rounding
+    bound = 4 * math.exp(-beta) + (1e-13 if prec == "fp64" else 1e-7)
+    assert worst <= bound, (w, beta, worst, bound)
+    # and well below the tolerance the plan was made for
+    assert worst <= eps / 10
