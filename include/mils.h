@@ -101,6 +101,9 @@ typedef struct {
   uint64_t workspace_bytes; /* device workspace the call needs */
   int32_t last_rows;   /* rows of length len[npass-1] per workgroup of the last pass */
   int32_t last_lds_bytes; /* dynamic LDS of one workgroup of the last pass */
+  int32_t first_cols;  /* columns per workgroup of the first pass (npass > 1) */
+  int32_t first_lds_bytes; /* dynamic LDS of one workgroup of the first pass (npass > 1) */
+  int32_t big;         /* 1: the passes run as 1024-thread workgroups with up to 160 KB LDS */
 } mils_plan_desc;
 
 /* Library version (MILS_VERSION of the build). */

@@ -443,10 +443,19 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
   out->bin = pl.Tb;
   out->workspace_bytes = layout_work(pl, nd, 3, nullptr, nullptr);
   {
+    // the launch sizes of kernels.hip
+    const size_t elem = pl.prec == 1 ? 8 : 16;
     const FftPass& lp = pl.pass[pl.npass - 1];
+    const int ntw_l = lp.big ? tw2_count(lp.L) : lp.L;
     out->last_rows = lp.C;
-    out->last_lds_bytes = (int32_t)((pl.prec == 1 ? 8 : 16) *
-                                    ((size_t)lp.L * last_pitch(3 * lp.C) + lp.L));
+    out->last_lds_bytes = (int32_t)(elem * ((size_t)lp.L * last_pitch(3 * lp.C) + ntw_l));
+    out->big = lp.big;
+    if (pl.npass > 1) {
+      const FftPass& fp = pl.pass[0];
+      const int ntw_f = fp.big ? tw2_count(fp.L) : fp.L;
+      out->first_cols = fp.C;
+      out->first_lds_bytes = (int32_t)(elem * ((size_t)fp.L * fp.C + ntw_f) + fp.L + 16);
+    }
   }
   return MILS_OK;
 }

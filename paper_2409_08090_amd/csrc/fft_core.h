@@ -10,6 +10,7 @@
 #pragma once
 
 #include "device_math.h"
+#include "mils_internal.h"
 
 namespace mils {
 
@@ -103,6 +104,59 @@ __device__ __forceinline__ void dft8(T2* a) {
   a[7] = csub(e[3], o3);
 }
 
+// 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2] for each n2, twiddles
+// exp(+2 pi i n2 k1 / 16), then DFT4 over n2; output k1 + 4 k2.
+template <typename T2>
+__device__ __forceinline__ void dft16(T2* a) {
+  using R = decltype(a[0].x);
+  const R c1 = (R)0.92387953251128675612818318939679;  // cos(pi / 8)
+  const R s1 = (R)0.38268343236508977172845998403040;  // sin(pi / 8)
+  const R h = (R)0.70710678118654752440084436210485;
+  T2 y[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    T2 t[4] = {a[n2], a[n2 + 4], a[n2 + 8], a[n2 + 12]};
+    dft4(t);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+  }
+  // exp(+2 pi i j / 16) for j = n2 k1 in {1, 2, 3, 4, 6, 9}
+  auto rot = [&](T2 v, R c, R s) {
+    T2 r;
+    r.x = v.x * c - v.y * s;
+    r.y = v.x * s + v.y * c;
+    return r;
+  };
+  auto rot45 = [&](T2 v) {  // j = 2
+    T2 r;
+    r.x = h * (v.x - v.y);
+    r.y = h * (v.x + v.y);
+    return r;
+  };
+  auto rot135 = [&](T2 v) {  // j = 6
+    T2 r;
+    r.x = -h * (v.x + v.y);
+    r.y = h * (v.x - v.y);
+    return r;
+  };
+  y[1][1] = rot(y[1][1], c1, s1);
+  y[1][2] = rot45(y[1][2]);
+  y[1][3] = rot(y[1][3], s1, c1);
+  y[2][1] = rot45(y[2][1]);
+  y[2][2] = cmuli(y[2][2]);
+  y[2][3] = rot135(y[2][3]);
+  y[3][1] = rot(y[3][1], s1, c1);
+  y[3][2] = rot135(y[3][2]);
+  y[3][3] = rot(y[3][3], -c1, -s1);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    T2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+    dft4(t);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+  }
+}
+
 template <int R, typename T2>
 __device__ __forceinline__ void dft(T2* a) {
   if constexpr (R == 2) dft2(a);
@@ -110,6 +164,7 @@ __device__ __forceinline__ void dft(T2* a) {
   else if constexpr (R == 4) dft4(a);
   else if constexpr (R == 5) dft5(a);
   else if constexpr (R == 8) dft8(a);
+  else if constexpr (R == 16) dft16(a);
 }
 
 // Quotient floor(j / d) for 0 <= j < 2048, 1 <= d <= 1024, given
@@ -119,6 +174,15 @@ __device__ __forceinline__ float fdiv_recip(int d) {
   return __builtin_amdgcn_rcpf((float)d) * 1.000244140625f;
 }
 __device__ __forceinline__ int fdiv_small(int j, float r) { return (int)((float)j * r); }
+
+// exp(2 pi i x / L) from the pass's LDS table: the full table, or (TW2) the
+// two-level one, lo[x mod kTwLo] * hi[x / kTwLo] with hi after the kTwLo lo.
+template <bool TW2, typename T2>
+__device__ __forceinline__ T2 tw_at(const T2* tw, int x) {
+  static_assert(kTwLo == 64, "two-level split by 6 bits");
+  if constexpr (TW2) return cmul(tw[kTwLo + (x >> 6)], tw[x & (kTwLo - 1)]);
+  else return tw[x];
+}
 
 // Per-thread walk over the butterflies (or elements) idx = tid + b*NT of a
 // set of ncol columns, idx = j*ncol + col: the first (j, col) takes one
@@ -148,7 +212,7 @@ struct ColWalk {
 // consecutive columns of one butterfly, so the R reads and writes of a wave
 // are runs of ncol contiguous elements).  All index arithmetic is 32-bit with
 // 24-bit products: L <= 1024 and ls * L fits easily.
-template <int R, int MAXB, int NT, typename T2>
+template <int R, int MAXB, int NT, bool TW2, typename T2>
 __device__ __forceinline__ void stockham_stage(T2* buf, int L, int ls, int Ns, const T2* twL,
                                                ColWalk w) {
   const int nb = L / R;
@@ -170,7 +234,7 @@ __device__ __forceinline__ void stockham_stage(T2* buf, int L, int ls, int Ns, c
       if (Ns > 1) {
         const int kt = __mul24(k, twstride);
 #pragma unroll
-        for (int q = 1; q < R; ++q) v[b][q] = cmul(v[b][q], twL[q * kt]);
+        for (int q = 1; q < R; ++q) v[b][q] = cmul(v[b][q], tw_at<TW2>(twL, q * kt));
       }
       dft<R>(v[b]);
       wofs[b] = w.col + __mul24(__mul24(jq, Ns * R) + k, ls);
@@ -189,8 +253,9 @@ __device__ __forceinline__ void stockham_stage(T2* buf, int L, int ls, int Ns, c
 }
 
 // Full transform of the ncol columns: runs the stages of the radix plan.
-// EMAX bounds L * ncol (it sizes the per-thread register arrays).
-template <int EMAX, int NT, typename T2>
+// EMAX bounds L * ncol (it sizes the per-thread register arrays); TW2 selects
+// the two-level twiddle table.
+template <int EMAX, int NT, bool TW2 = false, typename T2>
 __device__ __forceinline__ void lds_fft(T2* buf, int L, int ncol, int ls, const int* rad, int nrad,
                         const T2* twL) {
   const ColWalk w(threadIdx.x, NT, ncol);
@@ -199,19 +264,22 @@ __device__ __forceinline__ void lds_fft(T2* buf, int L, int ncol, int ls, const 
     int r = rad[s];
     switch (r) {
       case 2:
-        stockham_stage<2, (EMAX / 2 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
+        stockham_stage<2, (EMAX / 2 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
         break;
       case 3:
-        stockham_stage<3, (EMAX / 3 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
+        stockham_stage<3, (EMAX / 3 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
         break;
       case 4:
-        stockham_stage<4, (EMAX / 4 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
+        stockham_stage<4, (EMAX / 4 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
         break;
       case 5:
-        stockham_stage<5, (EMAX / 5 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
+        stockham_stage<5, (EMAX / 5 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
+        break;
+      case 8:
+        stockham_stage<8, (EMAX / 8 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
         break;
       default:
-        stockham_stage<8, (EMAX / 8 + NT - 1) / NT, NT>(buf, L, ls, Ns, twL, w);
+        stockham_stage<16, (EMAX / 16 + NT - 1) / NT, NT, TW2>(buf, L, ls, Ns, twL, w);
         break;
     }
     Ns *= r;

@@ -279,10 +279,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
 // ============================================================================
 // Row classification for the spread: the flag of every row of geometry GEO
 // (1 if a kernel support reaches it) and the list of active rows in order.
-// One workgroup of kRowThreads threads; nrows <= kRowThreads (nrows is the
-// first FFT length, at most kLmax).
+// One workgroup of kRowThreads threads; thread i takes the rows
+// [i*rpt, (i+1)*rpt) (rpt = ceil(nrows / kRowThreads)), so their order
+// survives one scan of the per-thread counts.
 constexpr int kRowThreads = 1024;
-static_assert(kLmax <= kRowThreads, "one thread per row");
+static_assert(kRowsMax <= kRowThreads * 32, "row flags of a thread fit one word");
 template <int GEO>
 __global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int nd,
                                                            unsigned char* rowflag, int* act_rows,
@@ -290,23 +291,31 @@ __global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int n
   __shared__ int scan[kRowThreads];
   const DevStats* st = w.stats;
   if (st->status != 0) return;
-  const int r = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int nrows = (int)p.nrows;
+  const int rpt = (nrows + kRowThreads - 1) / kRowThreads;
+  const int r0 = tid * rpt;
   const int h = (int)ceil(p.hw) + 1;
-  int active = 0;
-  if (r < p.nrows) {
-    active = row_active<GEO>(r, h, p, w.bin_start, nd);
-    rowflag[r] = (unsigned char)active;
+  unsigned flags = 0;  // bit i: row r0 + i is active (rpt <= 32)
+  int cnt = 0;
+  for (int i = 0; i < rpt && r0 + i < nrows; ++i) {
+    const int active = row_active<GEO>(r0 + i, h, p, w.bin_start, nd);
+    rowflag[r0 + i] = (unsigned char)active;
+    flags |= (unsigned)active << i;
+    cnt += active;
   }
-  scan[r] = active;
+  scan[tid] = cnt;
   __syncthreads();
   for (int off = 1; off < kRowThreads; off <<= 1) {
-    const int x = r >= off ? scan[r - off] : 0;
+    const int x = tid >= off ? scan[tid - off] : 0;
     __syncthreads();
-    scan[r] += x;
+    scan[tid] += x;
     __syncthreads();
   }
-  if (active) act_rows[scan[r] - 1] = r;
-  if (r == kRowThreads - 1) w.nact[slot] = scan[r];
+  int pos = scan[tid] - cnt;
+  for (int i = 0; i < rpt && r0 + i < nrows; ++i)
+    if ((flags >> i) & 1u) act_rows[pos++] = r0 + i;
+  if (tid == kRowThreads - 1) w.nact[slot] = scan[tid];
 }
 
 // Spreading over the tiles of the active rows only (their list and count come
@@ -333,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Wo
 // ============================================================================
 // FFT passes.
 // ============================================================================
-template <typename Real, int EMAX, int NT>
+template <typename Real, int EMAX, int NT, bool TW2>
 __global__ __launch_bounds__(NT) void k_fft_pass(PassBufs<Real> b, FftPass ps,
                                                  const typename cplx<Real>::T* tw,
                                                  const DevStats* st) {
@@ -341,10 +350,10 @@ __global__ __launch_bounds__(NT) void k_fft_pass(PassBufs<Real> b, FftPass ps,
   if (st->status != 0) return;
   const int64_t blk = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
   const int g = blockIdx.y;
-  fft_pass_block<Real, EMAX, NT>(blk, b.in[g], b.out[g], b.rowflag[g], ps, tw, smem);
+  fft_pass_block<Real, EMAX, NT, TW2>(blk, b.in[g], b.out[g], b.rowflag[g], ps, tw, smem);
 }
 
-template <typename Real, int G, int EMAX, int NT>
+template <typename Real, int G, int EMAX, int NT, bool TW2>
 __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, Plan pl,
                                                  CallArgs a, const typename cplx<Real>::T* tw,
                                                  const double* inv_phihat, const DevStats* stp,
@@ -354,8 +363,8 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
   const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
   const int64_t blk = xcd_remap(blockIdx.x, nblk);
   const DevStats st = *stp;
-  fft_last_block<Real, G, EMAX, NT>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat, st, smem,
-                                    G == 3 ? lowfix : nullptr);
+  fft_last_block<Real, G, EMAX, NT, TW2>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat, st,
+                                         smem, G == 3 ? lowfix : nullptr);
 }
 
 // Direct FP64 sums A, B, B2 at the (at most kLowMax) frequencies nearest
@@ -449,6 +458,13 @@ static inline unsigned grid_for(int64_t work, int64_t cap) {
   return (unsigned)b;
 }
 
+// Dynamic LDS above the default 64 KB of a workgroup must be allowed per
+// kernel (the big FFT passes use up to kLdsBig).
+static void big_lds(const void* kern, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)bytes);
+}
+
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
                          const double* gphi, int q, hipStream_t s) {
   hipLaunchKernelGGL(k_phihat, dim3(grid_for(K + 1, 1 << 30)), dim3(kThreads), 0, s, inv_phihat,
@@ -463,6 +479,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   constexpr bool f64 = sizeof(Real) == 8;
   constexpr int EMID = f64 ? kEmid64 : kEmid32;
   constexpr int ELAST = f64 ? kElast64 : kElast32;
+  constexpr int EBIG = f64 ? kEbig64 : kEbig32;
   const int G = a.periodogram ? 3 : 1;
   auto mark = [&](int stage, int begin) {
     if (hook) hook->fn(hook->ud, stage, begin, s);
@@ -526,10 +543,18 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.rowflag[g] = (ip == 0) ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
     }
     const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-    const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ps.L) + (size_t)ps.L + 16;
+    const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
+    const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ntw) + (size_t)ps.L + 16;
     mark(kStagePass0 + ip, 1);
-    hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads>), dim3((unsigned)nblk, G),
-                       dim3(kThreads), lds, s, b, ps, tw, w.stats);
+    if (ps.big) {
+      auto kern = k_fft_pass<Real, EBIG, kThreadsBig, true>;
+      big_lds(reinterpret_cast<const void*>(kern), lds);
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, G), dim3(kThreadsBig), lds, s, b, ps, tw,
+                         w.stats);
+    } else {
+      hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads, false>), dim3((unsigned)nblk, G),
+                         dim3(kThreads), lds, s, b, ps, tw, w.stats);
+    }
     mark(kStagePass0 + ip, 0);
     if (ip > 0) {
       for (int g = 0; g < 3; ++g) {
@@ -548,16 +573,24 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.rowflag[g] = nullptr;
     }
     const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
-    const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ps.L);
+    const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
+    const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ntw);
     mark(kStageLast, 1);
-    if (a.periodogram)
-      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, kThreadsLast>), dim3((unsigned)nblk),
+    if (ps.big) {
+      auto kern = a.periodogram ? k_fft_last<Real, 3, EBIG, kThreadsBig, true>
+                                : k_fft_last<Real, 1, EBIG, kThreadsBig, true>;
+      big_lds(reinterpret_cast<const void*>(kern), lds);
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreadsBig), lds, s, b, ps, p, a, tw,
+                         w.inv_phihat, w.stats, w.lowfix);
+    } else if (a.periodogram) {
+      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, kThreadsLast, false>), dim3((unsigned)nblk),
                          dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
                          w.lowfix);
-    else
-      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, kThreadsLast>), dim3((unsigned)nblk),
+    } else {
+      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, kThreadsLast, false>), dim3((unsigned)nblk),
                          dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
                          w.lowfix);
+    }
     mark(kStageLast, 0);
   }
   return hipGetLastError();

@@ -24,7 +24,8 @@ struct FftPass {
   int64_t P, S;
   int nrad;
   int rad[kMaxRadixStages];
-  int64_t twL_off;         // exp(2 pi i x / L), x in [0, L)
+  int64_t twL_off;         // exp(2 pi i x / L), x in [0, L); two-level when big (see kTwLo)
+  int big;                 // 1: a "big" pass (kThreadsBig threads, up to kLdsBig bytes of LDS)
   int64_t twlo_off;        // exp(2 pi i x / (L S)), x in [0, 2^bshift)
   int64_t twhi_off;        // exp(2 pi i (x << bshift) / (L S))
   int bshift;
@@ -125,6 +126,16 @@ struct Work {
 constexpr int kStatsBlocks = 1024;
 constexpr int kThreads = 256;       // threads of most kernels
 constexpr int kThreadsLast = 512;   // threads of the last FFT pass
+// Big passes: one workgroup of kThreadsBig threads per CU holds a column (or
+// row) set of up to kEbig elements in LDS, so that two passes cover grids of
+// ~1e7 cells.  Their in-pass twiddles come from a two-level table in LDS:
+// exp(2 pi i x / L) = lo[x mod kTwLo] * hi[x / kTwLo].
+constexpr int kThreadsBig = 1024;
+constexpr int kEbig64 = 9600, kEbig32 = 19200;
+constexpr size_t kLdsBig = 163840;  // LDS of one workgroup (gfx950)
+constexpr int kTwLo = 64;
+constexpr int kRowsMax = 16384;     // rows of the spreading view [nrows][S1]
+__host__ __device__ constexpr inline int tw2_count(int L) { return kTwLo + (L + kTwLo - 1) / kTwLo; }
 constexpr int kTileMax = 1024;      // spreading tile (cells)
 constexpr int kSpreadGrid = 2048;   // workgroups of the persistent spread
 constexpr int kLmax = 1024;         // longest per-pass FFT length

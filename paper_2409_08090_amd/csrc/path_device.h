@@ -294,11 +294,11 @@ struct PassBufs {
 // p; loads L x C elements (C contiguous per row, 128-256 B segments),
 // transforms along L in LDS, applies the inter-pass twiddle and stores with
 // the outer index and k transposed.  One workgroup's share of the pass is the
-// logical block blk.  smem: L*C elements + L twiddles + L row flags.  C is a
-// power of two that divides NT, so a thread keeps one column c = tid mod C
-// and visits rows l0, l0 + NT/C, ... (l0 = tid / C): its global addresses are
-// a base plus uniform strides.
-template <typename Real, int EMAX, int NT>
+// logical block blk.  smem: L*C elements + the twiddle table (L entries, or
+// tw2_count(L) for TW2) + L row flags.  C is a power of two that divides NT,
+// so a thread keeps one column c = tid mod C and visits rows l0, l0 + NT/C,
+// ... (l0 = tid / C): its global addresses are a base plus uniform strides.
+template <typename Real, int EMAX, int NT, bool TW2 = false>
 __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
                                typename cplx<Real>::T* out, const unsigned char* rflag,
                                const FftPass& ps, const typename cplx<Real>::T* tw,
@@ -306,19 +306,18 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
   const int L = ps.L, C = ps.C, csh = ps.cshift;
+  const int ntw = TW2 ? tw2_count(L) : L;
   T2* buf = reinterpret_cast<T2*>(smem);
   T2* twL = buf + L * C;
-  unsigned char* rf = reinterpret_cast<unsigned char*>(twL + L);
+  unsigned char* rf = reinterpret_cast<unsigned char*>(twL + ntw);
   const int64_t S = ps.S, P = ps.P;
   const uint32_t nsb = (uint32_t)((S + C - 1) / C);
   const uint32_t pidx32 = (uint32_t)blk / nsb;
   const int64_t pidx = pidx32;
   const int64_t s0 = (int64_t)((uint32_t)blk - pidx32 * nsb) * C;
   const int ceff = (int)((S - s0) < C ? (S - s0) : C);
-  for (int x = tid; x < L; x += NT) {
-    twL[x] = tw[ps.twL_off + x];
-    rf[x] = rflag ? rflag[x] : (unsigned char)1;
-  }
+  for (int x = tid; x < ntw; x += NT) twL[x] = tw[ps.twL_off + x];
+  for (int x = tid; x < L; x += NT) rf[x] = rflag ? rflag[x] : (unsigned char)1;
   const int c = tid & (C - 1);
   const int l0 = tid >> csh;
   const int LS = NT >> csh;  // rows between a thread's consecutive elements
@@ -353,7 +352,7 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
   const T2 w0 = cmul(thi[q0 >> ps.bshift], tlo[q0 & mask]);
   const T2 ws = cmul(thi[qs >> ps.bshift], tlo[qs & mask]);
   __syncthreads();
-  lds_fft<EMAX, NT>(buf, L, C, C, ps.rad, ps.nrad, twL);
+  lds_fft<EMAX, NT, TW2>(buf, L, C, C, ps.rad, ps.nrad, twL);
   const int64_t PS = P * S;
   T2* pout = out + (int64_t)l0 * PS + pidx * S + s0 + c;
   const int64_t ostep = (int64_t)LS * PS;
@@ -409,10 +408,11 @@ __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, doub
 // run of consecutive elements, which the LDS serves without bank conflicts.
 // The global loads take the row index fastest (lanes (l, d), D rows of one
 // grid), so that their LDS stores are contiguous runs too while each row is
-// still read in contiguous 16-element pieces.  smem: L*R elements + L
-// twiddles.  nf and K are those of the series (a batched series may use fewer
-// frequencies than its grid's plan).
-template <typename Real, int G, int EMAX, int NT>
+// still read in contiguous 16-element pieces.  smem: L*R elements + the
+// twiddle table (L entries, or tw2_count(L) for TW2).  nf and K are those of
+// the series (a batched series may use fewer frequencies than its grid's
+// plan).
+template <typename Real, int G, int EMAX, int NT, bool TW2 = false>
 __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPass& ps,
                                int64_t n, int64_t nf, int64_t K, const CallArgs& a,
                                const typename cplx<Real>::T* tw, const double* inv_phihat,
@@ -427,7 +427,7 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
   const int64_t P = ps.P;
   const int64_t p0 = blk * D;
   const int deff = (int)((P - p0) < D ? (P - p0) : D);
-  for (int x = tid; x < L; x += NT) twL[x] = tw[ps.twL_off + x];
+  for (int x = tid; x < (TW2 ? tw2_count(L) : L); x += NT) twL[x] = tw[ps.twL_off + x];
   const int E = D * L;
   const int dsh = __builtin_ctz(D);  // D is a power of two
   constexpr int PER = (EMAX / G + NT - 1) / NT;
@@ -473,7 +473,7 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       }
     }
   }
-  lds_fft<EMAX, NT>(buf, L, G * D, R, ps.rad, ps.nrad, twL);
+  lds_fft<EMAX, NT, TW2>(buf, L, G * D, R, ps.rad, ps.nrad, twL);
 #pragma unroll
   for (int i = 0; i < PO; ++i) {
     const int64_t kout = kov[i];

@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 
 namespace mils {
@@ -27,6 +28,39 @@ constexpr size_t kLdsMax = 65536;        // dynamic LDS of one workgroup
 static bool last_lds_ok(int G, int d, int L, int prec) {
   const size_t elem = prec == 1 ? 8 : 16;
   return elem * ((size_t)L * (size_t)last_pitch(G * d) + (size_t)L) <= kLdsMax;
+}
+
+// Big passes (see kThreadsBig).  Columns per workgroup of a big first pass
+// (0 if none fits): the most contiguous columns (a power of two up to 8, at
+// least cmin) whose L x C tile, twiddles and row flags fit the LDS.
+static int big_cols(int L, int64_t S, int prec, int cmin) {
+  const size_t elem = prec == 1 ? 8 : 16;
+  const int emax = prec == 1 ? kEbig32 : kEbig64;
+  for (int c = 8; c >= cmin; c /= 2) {
+    if (c > S || (int64_t)L * c > emax) continue;
+    if (elem * ((size_t)L * c + tw2_count(L)) + (size_t)L + 64 <= kLdsBig) return c;
+  }
+  return 0;
+}
+// Rows per workgroup of a big last pass over G grids (0 if none fits).
+static int big_rows(int L, int64_t P, int G, int prec) {
+  const size_t elem = prec == 1 ? 8 : 16;
+  const int emax = prec == 1 ? kEbig32 : kEbig64;
+  for (int d = 8; d >= 1; d /= 2) {
+    if (d > P || (int64_t)G * d * L > emax) continue;
+    if (elem * ((size_t)G * d * L + tw2_count(L)) <= kLdsBig) return d;
+  }
+  return 0;
+}
+// Big passes are opt-in (MILS_FFT_BIG=1): one workgroup per CU cannot
+// overlap its loads, transform and stores, and measured slower than three
+// small passes on the 1.5e7-cell grids.
+static bool big_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("MILS_FFT_BIG");
+    return e && e[0] == '1';
+  }();
+  return on;
 }
 
 std::vector<int64_t> smooth_in_range(int64_t lo, int64_t hi) {
@@ -46,9 +80,13 @@ bool is_smooth(int64_t x) {
   return x == 1;
 }
 
-// radix plan of a 5-smooth length: radix 8 and 4 first, then 2, 5, 3.
+// radix plan of a 5-smooth length: radix 16, 8 and 4 first, then 2, 5, 3.
 int radix_plan(int L, int* rad) {
   int n = 0;
+  while (L % 16 == 0) {
+    rad[n++] = 16;
+    L /= 16;
+  }
   while (L % 8 == 0 && L > 8) {
     rad[n++] = 8;
     L /= 8;
@@ -168,41 +206,105 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
 
   std::vector<int64_t> cand = r.n_fixed > 0 ? std::vector<int64_t>{r.n_fixed}
                                              : smooth_in_range(nmin, 2 * nmin + 64);
+  const int big_cmin = r.prec == 1 ? 4 : 2;
+  // Factorisation of n into np passes that fit (lens; big: two big passes).
+  auto factor = [&](int np, int64_t n, std::vector<int>* lens, bool* big) -> bool {
+    lens->clear();
+    *big = false;
+    if (np == 1) {
+      if (G * n <= elast && n <= kLmaxPass && last_lds_ok(G, 1, (int)n, r.prec)) {
+        lens->push_back((int)n);
+        return true;
+      }
+      return false;
+    }
+    // last length: largest with >= dmin rows per workgroup
+    const int llast_max = std::min<int64_t>(elast / (G * dmin), kLmaxPass);
+    for (int Ll = llast_max; Ll >= 2; --Ll) {
+      if (n % Ll || !is_smooth(Ll) || !last_lds_ok(G, dmin, Ll, r.prec)) continue;
+      std::vector<int> mids;
+      if (split_mid(n / Ll, np - 1, std::min(kLmaxPass, emid / 4), &mids)) {
+        *lens = mids;
+        lens->push_back(Ll);
+        return true;
+      }
+    }
+    // two big passes n = L0 * L1: most contiguous first-pass columns, then
+    // most rows per last-pass workgroup
+    if (np == 2 && !r.batch && big_enabled()) {
+      int bc = 0, bd = 0, bl = 0;
+      const int64_t l0_lo = std::max<int64_t>(2, (n + kEbig32 - 1) / kEbig32);
+      const int64_t l0_hi = std::min<int64_t>(kEbig32, n / 2);
+      for (int64_t L0 = l0_lo; L0 <= l0_hi; ++L0) {
+        if (n % L0 || !is_smooth(L0)) continue;
+        const int64_t L1 = n / L0;
+        if (L1 > kEbig32) continue;
+        const int c = big_cols((int)L0, L1, r.prec, big_cmin);
+        const int d = c ? big_rows((int)L1, L0, G, r.prec) : 0;
+        if (!c || !d) continue;
+        if (c > bc || (c == bc && d > bd)) {
+          bc = c;
+          bd = d;
+          bl = (int)L0;
+        }
+      }
+      if (bl) {
+        *lens = {bl, (int)(n / bl)};
+        *big = true;
+        return true;
+      }
+    }
+    return false;
+  };
+  // Estimated time of a plan, in units of one FFT pass over one cell
+  // (calibrated on the 1.5e7-cell grids): a first pass weighs 0.8, a middle
+  // pass 1.1, the last pass 1.0 and a single in-LDS pass 0.3, each 7% more
+  // (less) per radix stage above (below) four and 15% per halving of the row
+  // pieces below 128 B; the spread adds ~0.049 w per
+  // frequency (points ~ N_f / 12, the usual sampling).  Among the smooth sizes
+  // up to 1.3 x the minimum this trades a slightly larger grid for fewer
+  // stages and a narrower kernel.
+  auto estimate = [&](int64_t n, const std::vector<int>& lens) -> double {
+    const int np = (int)lens.size();
+    int rad[kMaxRadixStages];
+    double sum = 0.0;
+    const int elem = r.prec == 1 ? 8 : 16;
+    for (int i = 0; i < np; ++i) {
+      const double wt = np == 1 ? 0.3 : (i == 0 ? 0.8 : (i + 1 == np ? 1.0 : 1.1));
+      const int st = radix_plan(lens[i], rad);
+      double f = wt * (1.0 + 0.07 * (st - 4));
+      // a first/middle pass moves rows of C columns: below 128 B per row
+      // piece each halving costs ~15%
+      if (np > 1 && i + 1 < np) {
+        const int c = std::min(cmax, pow2_floor(emid / lens[i]));
+        for (int bytes = c * elem; bytes < 128; bytes *= 2) f *= 1.15;
+      }
+      sum += f;
+    }
+    const int wn = kernel_width(r.eps, (double)n / (double)r.nf, r.prec);
+    return (double)n * sum + 0.049 * wn * (double)r.nf;
+  };
   double best_cost = 1e300;
   int best_np = 0;
   int64_t best_n = 0;
+  bool best_big = false;
   std::vector<int> best_len;
-  for (int np = 1; np <= kMaxPass; ++np) {
-    for (int64_t n : cand) {
-      double cost = (double)n * (np == 1 ? 1.0 : 2.0 * np - 1.0);
-      if (cost >= best_cost) break;
+  const double nlim = 1.3 * (double)nmin;
+  for (int64_t n : cand) {
+    if (best_np && (double)n > nlim) break;
+    for (int np = 1; np <= kMaxPass; ++np) {
       std::vector<int> lens;
-      bool ok = false;
-      if (np == 1) {
-        if (G * (n + 1) <= elast && n <= kLmaxPass && last_lds_ok(G, 1, (int)n, r.prec)) {
-          lens.push_back((int)n);
-          ok = true;
-        }
-      } else {
-        // last length: largest with >= dmin rows per workgroup
-        const int llast_max = std::min<int64_t>(elast / (G * dmin) - 1, kLmaxPass);
-        for (int Ll = llast_max; Ll >= 2 && !ok; --Ll) {
-          if (n % Ll || !is_smooth(Ll) || !last_lds_ok(G, dmin, Ll, r.prec)) continue;
-          std::vector<int> mids;
-          if (split_mid(n / Ll, np - 1, std::min(kLmaxPass, emid / 4), &mids)) {
-            lens = mids;
-            lens.push_back(Ll);
-            ok = true;
-          }
-        }
-      }
-      if (ok) {
+      bool big = false;
+      if (!factor(np, n, &lens, &big)) continue;
+      const double cost = estimate(n, lens);
+      if (cost < best_cost) {
         best_cost = cost;
         best_np = np;
         best_n = n;
+        best_big = big;
         best_len = lens;
-        break;
       }
+      break;  // more passes over the same n only cost more
     }
   }
   if (!best_np) {
@@ -228,6 +330,18 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     ps.S = best_n / (before * ps.L);
     before *= ps.L;
     ps.nrad = radix_plan(ps.L, ps.rad);
+    ps.big = best_big ? 1 : 0;
+    if (best_big) {
+      if (i == 0) {
+        ps.C = big_cols(ps.L, ps.S, r.prec, big_cmin);
+        ps.cshift = 0;
+        while ((1 << ps.cshift) < ps.C) ++ps.cshift;
+      } else {
+        ps.C = big_rows(ps.L, ps.P, G, r.prec);
+        p.D = ps.C;
+      }
+      continue;
+    }
     if (i + 1 < best_np) {
       int c = std::min(cmax, pow2_floor(emid / ps.L));
       while (c > 1 && c / 2 >= ps.S) c /= 2;
@@ -236,10 +350,10 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
       while ((1 << ps.cshift) < c) ++ps.cshift;
     } else {
       int d = 1;
-      while (d < 8 && G * (2 * d) * (ps.L + 1) <= elast && 2 * d <= ps.P &&
+      while (d < 8 && G * (2 * d) * ps.L <= elast && 2 * d <= ps.P &&
              last_lds_ok(G, 2 * d, ps.L, r.prec))
         d *= 2;
-      if (G * d * (ps.L + 1) > elast || !last_lds_ok(G, d, ps.L, r.prec)) {
+      if (G * d * ps.L > elast || !last_lds_ok(G, d, ps.L, r.prec)) {
         if (err) *err = "last FFT pass does not fit one workgroup";
         return false;
       }
@@ -253,6 +367,10 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   } else {
     p.nrows = p.pass[0].L;
     p.S1 = best_n / p.nrows;
+    if (p.nrows > kRowsMax) {
+      if (err) *err = "first FFT pass longer than the spreading view allows";
+      return false;
+    }
   }
   int T = 1;
   for (int d = (int)std::min<int64_t>(p.S1, kTileMaxCells); d >= 1; --d)
@@ -278,7 +396,12 @@ void make_twiddles(Plan* p, std::vector<double>* tw) {
   for (int i = 0; i < p->npass; ++i) {
     FftPass& ps = p->pass[i];
     ps.twL_off = (int64_t)(tw->size() / 2);
-    for (int x = 0; x < ps.L; ++x) push_root(x, ps.L);
+    if (ps.big) {
+      for (int x = 0; x < kTwLo; ++x) push_root(x, ps.L);
+      for (int h = 0; h < (ps.L + kTwLo - 1) / kTwLo; ++h) push_root((int64_t)h * kTwLo, ps.L);
+    } else {
+      for (int x = 0; x < ps.L; ++x) push_root(x, ps.L);
+    }
     if (i + 1 < p->npass) {
       const int64_t N = (int64_t)ps.L * ps.S;
       int b = 0;

@@ -42,7 +42,8 @@ class mils_plan_desc(ctypes.Structure):
                 ("n", ctypes.c_int64), ("npass", ctypes.c_int32), ("len", ctypes.c_int32 * 4),
                 ("tile", ctypes.c_int32), ("bin", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_uint64), ("last_rows", ctypes.c_int32),
-                ("last_lds_bytes", ctypes.c_int32)]
+                ("last_lds_bytes", ctypes.c_int32), ("first_cols", ctypes.c_int32),
+                ("first_lds_bytes", ctypes.c_int32), ("big", ctypes.c_int32)]
 
 
 class mils_server_config(ctypes.Structure):
@@ -244,7 +245,8 @@ def plan_info(nd, nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01) -> dict:
     out = {"sigma": d.sigma, "width": d.width, "beta": d.beta, "n": d.n, "npass": d.npass,
            "len": list(d.len)[:d.npass], "tile": d.tile, "bin": d.bin,
            "workspace_bytes": d.workspace_bytes, "last_rows": d.last_rows,
-           "last_lds_bytes": d.last_lds_bytes}
+           "last_lds_bytes": d.last_lds_bytes, "first_cols": d.first_cols,
+           "first_lds_bytes": d.first_lds_bytes, "big": d.big}
     ctx.close()
     return out
 

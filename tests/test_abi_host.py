@@ -126,18 +126,47 @@ def test_planner_invariants(nf, eps, prec):
     margin = 8 if prec == "fp64" else 2
     assert math.exp(-math.pi * d["width"] * math.sqrt(1 - 1 / d["sigma"])) <= eps / margin * 1.0001
     assert n % d["tile"] == 0 and d["tile"] <= 1024
-    assert 1 <= d["last_rows"] <= 8 and 0 < d["last_lds_bytes"] <= 65536
+    assert 1 <= d["last_rows"] <= 8 and 0 < d["last_lds_bytes"] <= 163840
+
+
+def _tw2(L):
+    return 64 + (L + 63) // 64
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_last_pass_fits_one_workgroup_over_a_size_sweep(prec):
-    # the last pass keeps L * pitch + L elements in LDS (pitch = 3 rows)
+def test_fft_passes_fit_one_workgroup_over_a_size_sweep(prec):
+    # LDS of a workgroup: last pass L * 3D elements + twiddles, first pass
+    # L * C elements + twiddles + L row flags; twiddles are L entries, or the
+    # two-level table of big passes (1024 threads, up to 160 KB of LDS)
+    elem = 16 if prec == "fp64" else 8
     for nf in sorted({int(x) for x in np.geomspace(1, 3e7, 300)}):
         d = mils.plan_info(nd=1000, nf=nf, eps=1e-9 if prec == "fp64" else 1e-5, precision=prec)
-        L, D = d["len"][-1], d["last_rows"]
-        elem = 16 if prec == "fp64" else 8
-        assert d["last_lds_bytes"] == elem * (L * 3 * D + L) <= 65536, (nf, d)
-        assert 3 * D * L <= (3072 if prec == "fp64" else 6144), (nf, d)
+        L, D, big = d["len"][-1], d["last_rows"], d["big"]
+        cap, emax = (163840, 9600 if prec == "fp64" else 19200) if big else \
+            (65536, 3072 if prec == "fp64" else 6144)
+        ntw = _tw2(L) if big else L
+        assert d["last_lds_bytes"] == elem * (L * 3 * D + ntw) <= cap, (nf, d)
+        assert 3 * D * L <= emax, (nf, d)
+        if d["npass"] > 1:
+            L0, C = d["len"][0], d["first_cols"]
+            assert C & (C - 1) == 0 and (not big or C >= (2 if prec == "fp64" else 4)), (nf, d)
+            assert d["first_lds_bytes"] == elem * (L0 * C + (_tw2(L0) if big else L0)) + L0 + 16
+            assert d["first_lds_bytes"] <= cap and L0 * C <= (emax if big else emax * 2 // 3), (nf, d)
+        if big:
+            assert d["npass"] == 2
+
+
+def test_large_curve_plans():
+    # the N_f = 1.2e7 curve: three small passes by default, two big ones on request
+    import subprocess, sys
+    for prec, eps in (("fp64", 1e-9), ("fp32", 1e-5)):
+        d = mils.plan_info(nd=1_000_000, nf=12_000_000, eps=eps, precision=prec)
+        assert d["npass"] == 3 and d["big"] == 0, d
+    code = ("from paper_2409_08090_amd import mils; "
+            "d = mils.plan_info(1_000_000, 12_000_000, 1e-9); print(d['npass'], d['big'])")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         env={**os.environ, "MILS_FFT_BIG": "1"}, check=True).stdout.split()
+    assert out == ["2", "1"]
 
 
 def test_kernel_error_estimate_falls_with_tolerance():
@@ -151,9 +180,15 @@ def test_kernel_error_estimate_falls_with_tolerance():
     assert ws == sorted(ws) and ws[0] < ws[-1]
 
 
-def test_cfg1_shape_uses_three_lds_passes():
+def test_large_curve_grid_and_width():
+    # the planner may trade a slightly larger grid (sigma up to ~1.3 x 1.25)
+    # for fewer radix stages and a narrower kernel; the width still meets eps
     d = mils.plan_info(nd=1_000_000, nf=12_000_000, eps=1e-9)
-    assert d["npass"] == 3 and d["n"] >= 15_000_000 and d["width"] == 17
+    assert 15_000_000 <= d["n"] <= 1.3 * 15_000_000
+    w, sigma = d["width"], d["sigma"]
+    assert math.exp(-math.pi * w * math.sqrt(1 - 1 / sigma)) <= 1e-9 / 8 * 1.0001
+    assert math.exp(-math.pi * (w - 1) * math.sqrt(1 - 1 / sigma)) > 1e-9 / 8  # no wider than needed
+    assert math.prod(d["len"]) == d["n"]
 
 
 def test_server_config_and_device_checks():
