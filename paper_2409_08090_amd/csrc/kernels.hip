@@ -364,7 +364,7 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
   const int64_t blk = xcd_remap(blockIdx.x, nblk);
   const DevStats st = *stp;
   fft_last_block<Real, G, EMAX, NT, TW2>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat, st,
-                                         smem, G == 3 ? lowfix : nullptr);
+                                         smem, G == 3 ? lowfix : nullptr, kLowParts);
 }
 
 // Direct FP64 sums A, B, B2 at the (at most kLowMax) frequencies nearest
@@ -407,9 +407,16 @@ __global__ __launch_bounds__(kThreads) void k_lowfreq(CallArgs a, Work w) {
   }
 }
 
-// value x = idx / 8 is summed over blocks b = idx % 8 (mod 8) by one thread,
-// then over the 8 lanes that hold its parts
-__global__ __launch_bounds__(kThreads) void k_lowfreq_final(CallArgs a, Work w, int nparts) {
+// Block r of kLowParts adds the block totals [r*nparts/kLowParts,
+// (r+1)*nparts/kLowParts) into row r of lowfix (one workgroup alone could
+// not read the partials faster than one CU's bandwidth); the last pass adds
+// the rows.  Thread (x, pr) of 8 x kLowNV adds value x over the blocks of its
+// share congruent to pr mod 8 with eight independent partial sums, then the 8
+// parts of x are combined across lanes.  Fixed order throughout, so the
+// result does not depend on timing.
+constexpr int kLowFinalThreads = 8 * kLowNV;
+__global__ __launch_bounds__(kLowFinalThreads) void k_lowfreq_final(CallArgs a, Work w,
+                                                                    int nparts) {
   DevStats* stp = w.stats;
   const DevStats st = *stp;
   if (st.status != 0 || !a.periodogram) return;
@@ -418,16 +425,25 @@ __global__ __launch_bounds__(kThreads) void k_lowfreq_final(CallArgs a, Work w, 
   low_band(st, a.f0, a.df, a.nf, k_lo, nlow);
   if (nlow == 0) return;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kLowNV * 8; idx += kThreads) {
-    const int x = idx >> 3, pr = idx & 7;
-    double sum = 0.0;
-    for (int b = pr; b < nparts; b += 8) sum += w.lowpart[(size_t)b * kLowNV + x];
-    sum += __shfl_xor(sum, 1, 64);
-    sum += __shfl_xor(sum, 2, 64);
-    sum += __shfl_xor(sum, 4, 64);
-    if (pr == 0 && x < 6 * nlow) w.lowfix[x] = sum;
+  const int x = tid >> 3, pr = tid & 7;
+  const int r = blockIdx.x;
+  const int b0 = (int)(((int64_t)nparts * r) / kLowParts);
+  const int b1 = (int)(((int64_t)nparts * (r + 1)) / kLowParts);
+  double part[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) part[u] = 0.0;
+  int b = b0 + pr;
+  for (; b + 56 < b1; b += 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] += w.lowpart[(size_t)(b + 8 * u) * kLowNV + x];
   }
-  if (tid == 0) {
+  for (int u = 0; b < b1; b += 8, ++u) part[u & 7] += w.lowpart[(size_t)b * kLowNV + x];
+  double sum = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
+  sum += __shfl_xor(sum, 1, 64);
+  sum += __shfl_xor(sum, 2, 64);
+  sum += __shfl_xor(sum, 4, 64);
+  if (pr == 0 && x < 6 * nlow) w.lowfix[r * kLowNV + x] = sum;
+  if (r == 0 && tid == 0) {
     stp->k_lo = k_lo;
     stp->nlow = nlow;
   }
@@ -490,7 +506,8 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   if (a.periodogram) {
     const unsigned lb = grid_for(a.nd, kLowBlocks);
     hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s, a, w);
-    hipLaunchKernelGGL(k_lowfreq_final, dim3(1), dim3(kThreads), 0, s, a, w, (int)lb);
+    hipLaunchKernelGGL(k_lowfreq_final, dim3(kLowParts), dim3(kLowFinalThreads), 0, s, a, w,
+                       (int)lb);
   }
   mark(kStageStats, 0);
   mark(kStageBin, 1);

@@ -120,7 +120,7 @@ struct Work {
   const void* tw;         // twiddles (plan-owned)
   const double* inv_phihat;  // 1 / phihat(|m|), m = 0..K (plan-owned)
   double* lowpart;        // per-block partial direct sums near f = 0
-  double* lowfix;         // direct sums A, B, B2 near f = 0 (kLowMax x 6)
+  double* lowfix;         // direct sums A, B, B2 near f = 0: kLowParts rows of kLowMax x 6
 };
 
 constexpr int kStatsBlocks = 1024;
@@ -137,7 +137,7 @@ constexpr int kTwLo = 64;
 constexpr int kRowsMax = 16384;     // rows of the spreading view [nrows][S1]
 __host__ __device__ constexpr inline int tw2_count(int L) { return kTwLo + (L + kTwLo - 1) / kTwLo; }
 constexpr int kTileMax = 1024;      // spreading tile (cells)
-constexpr int kSpreadGrid = 2048;   // workgroups of the persistent spread
+constexpr int kSpreadGrid = 4096;   // workgroups of the persistent spread
 constexpr int kLmax = 1024;         // longest per-pass FFT length
 // elements held in LDS by one workgroup of a first/middle pass and of the last pass
 constexpr int kEmid64 = 2048, kEmid32 = 4096;
@@ -152,6 +152,7 @@ constexpr int kBatchLds = 65536;    // dynamic LDS of the batched kernel
 constexpr int kLowMax = 16;
 constexpr int kLowGroup = 8;
 constexpr int kLowBlocks = 512;
+constexpr int kLowParts = 8;  // rows of lowfix (partial sums; the last pass adds them)
 
 // LDS pitch of the last FFT pass: its rows are interleaved element by element
 // with no padding.

@@ -417,7 +417,7 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
                                int64_t n, int64_t nf, int64_t K, const CallArgs& a,
                                const typename cplx<Real>::T* tw, const double* inv_phihat,
                                const DevStats& st, unsigned char* smem,
-                               const double* lowfix = nullptr) {
+                               const double* lowfix = nullptr, int lowparts = 1) {
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
   const int L = ps.L, D = ps.C;
@@ -489,8 +489,11 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       double s6[6] = {(double)A.x * ip,  (double)A.y * ip,  (double)B.x * ip,
                       (double)B.y * ip,  (double)B2.x * ip, (double)B2.y * ip};
       const int64_t q = kout - st.k_lo;
-      if (lowfix && q >= 0 && q < st.nlow)
+      if (lowfix && q >= 0 && q < st.nlow) {
         for (int j = 0; j < 6; ++j) s6[j] = lowfix[6 * q + j];
+        for (int r = 1; r < lowparts; ++r)
+          for (int j = 0; j < 6; ++j) s6[j] += lowfix[r * 6 * kLowMax + 6 * q + j];
+      }
       double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean);
       if (kout == a.kzero) pw = 0.0;
       a.power[kout] = pw;

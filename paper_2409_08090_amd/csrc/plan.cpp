@@ -482,7 +482,7 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
     x.hs = reinterpret_cast<double*>(take(sizeof(double) * nd));
   }
   x.lowpart = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowBlocks));
-  x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax));
+  x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowParts));
   x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.act_rows_f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
