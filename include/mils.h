@@ -187,7 +187,14 @@ int mils_context_status(mils_context *ctx);
  * are device arrays (dy may be NULL).  common supplies eps, precision,
  * normalization and flags (its f0, df, nf are ignored).  status_per_curve
  * (host, nullable, ncurves int32) receives each curve's device-side status.
- * Synchronous.
+ * Synchronous.  The series run together, phase by phase (per-series
+ * statistics, binning and low-frequency sums; both spreads; each FFT pass;
+ * the last pass with power), each phase one launch over the tiles of every
+ * series; the launches of a batch layout are captured once in a HIP graph
+ * and replayed by later calls with the same layout and pointers.  Every
+ * series has its own device workspace (its three grids, 48 bytes per grid
+ * cell in FP64 and 24 in FP32, plus binning buffers); a batch that needs more
+ * than the context's budget allows (or 24 GiB) runs in chunks.
  */
 int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd_off,
                            const double *t, const double *y, const double *dy,

@@ -77,17 +77,19 @@ uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
 // State of the batched path kept between calls: the uploaded descriptors, the
 // slot workspace and the captured graph are reused when the next batch has
 // the same layout and parameters.
+// Per-series workspaces of one chunk of a batch are limited to this (the
+// batch runs chunk after chunk when the series need more).
+constexpr size_t kBatchWorkspaceCap = (size_t)24 << 30;
+
 struct BatchState {
   uint64_t key = 0;
   bool valid = false;
-  char* dev = nullptr;  // descriptors, plans, table pointers, status, counter
+  char* dev = nullptr;  // descriptors, plans, table pointers, workspaces' layout, items, status
   size_t dev_bytes = 0;
-  char* ws = nullptr;   // slot workspaces
+  char* ws = nullptr;   // per-series workspaces (of the largest chunk)
   size_t ws_bytes = 0;
-  int nslots = 0;
-  int prec = 0;
   int64_t ncurves = 0;
-  mils::BatchArgs args{};
+  std::vector<mils::BatchLaunch> launches;  // one per chunk, in order
   int* status_dev = nullptr;
   int32_t* status_host = nullptr;  // pinned
   size_t status_cap = 0;
@@ -598,8 +600,6 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
     std::vector<Plan> plans(ncls);
     std::vector<const void*> twp(ncls);
     std::vector<const double*> php(ncls);
-    Plan big{};
-    int64_t nd_max = 1;
     for (int k = 0; k < ncls; ++k) {
       PlanEntry* pe = nullptr;
       int rc = get_plan(ctx, cls_nf[k], common->eps, prec, 3, &pe, true, true, cls_n[k]);
@@ -607,19 +607,12 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
       plans[k] = pe->plan;
       twp[k] = pe->tw;
       php[k] = pe->inv_phihat;
-      const Plan& q = pe->plan;
-      big.prec = prec;
-      big.n = std::max(big.n, q.n);
-      big.nbins = std::max(big.nbins, q.nbins);
-      big.nrows = std::max(big.nrows, q.nrows);
-      big.npass = std::max(big.npass, q.npass);
     }
-    for (int64_t c = 0; c < ncurves; ++c) nd_max = std::max(nd_max, nd_off[c + 1] - nd_off[c]);
-    // descriptors ordered by decreasing estimated cost
+    // series descriptors and their workspaces; chunks whose workspaces fit the cap
     std::vector<BatchCurve> cur(ncurves);
+    std::vector<size_t> wsz(ncurves);
     for (int64_t c = 0; c < ncurves; ++c) {
       BatchCurve& d = cur[c];
-      const Plan& q = plans[cls_of[c]];
       d.t_off = nd_off[c];
       d.nd = nd_off[c + 1] - nd_off[c];
       d.out_off = nf_off[c];
@@ -631,33 +624,82 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
       d.kzero = zero_index(d.f0, d.df, d.nf);
       d.plan = cls_of[c];
       d.index = (int)c;
-      (void)q;
+      wsz[c] = (layout_work(plans[cls_of[c]], d.nd, 3, nullptr, nullptr, true) + 255) & ~(size_t)255;
     }
-    std::vector<double> cost(ncurves);
+    size_t cap = kBatchWorkspaceCap;
+    if (ctx->budget) {
+      const size_t used = ctx->plan_bytes + ctx->ws_bytes;
+      cap = ctx->budget > used ? std::min<size_t>(cap, (ctx->budget - used) / 2) : 0;
+    }
+    std::vector<int64_t> chunk_begin{0};
+    size_t acc = 0, ws_max = 0;
     for (int64_t c = 0; c < ncurves; ++c) {
-      const Plan& q = plans[cls_of[c]];
-      cost[c] = (double)q.n * (2.0 * q.npass + 1.0) * 3.0 + (double)cur[c].nd * q.w * 3.0;
+      if (wsz[c] > cap) return fail(ctx, MILS_ERR_OOM, "a series of the batch exceeds the HBM budget");
+      if (acc + wsz[c] > cap) {
+        chunk_begin.push_back(c);
+        ws_max = std::max(ws_max, acc);
+        acc = 0;
+      }
+      acc += wsz[c];
     }
-    std::vector<int64_t> order(ncurves);
-    for (int64_t c = 0; c < ncurves; ++c) order[c] = c;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
-    std::vector<BatchCurve> sorted(ncurves);
-    for (int64_t i = 0; i < ncurves; ++i) sorted[i] = cur[order[i]];
-
-    // device buffers
+    ws_max = std::max(ws_max, acc);
+    chunk_begin.push_back(ncurves);
+    const int nchunks = (int)chunk_begin.size() - 1;
+    // work items of every chunk
+    struct ChunkItems {
+      std::vector<BatchItem> spread, pass[kMaxPass - 1], last;
+    };
+    std::vector<ChunkItems> ci(nchunks);
+    for (int k = 0; k < nchunks; ++k) {
+      for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
+        const Plan& q = plans[cls_of[c]];
+        const int lc = (int)(c - chunk_begin[k]);
+        for (int64_t tl = 0; tl < q.n / q.T; ++tl) ci[k].spread.push_back({lc, (int)tl});
+        for (int ip = 0; ip + 1 < q.npass; ++ip) {
+          const FftPass& ps = q.pass[ip];
+          const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
+          for (int64_t x = 0; x < 3 * nblk; ++x) ci[k].pass[ip].push_back({lc, (int)x});
+        }
+        const FftPass& ls = q.pass[q.npass - 1];
+        for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x});
+      }
+    }
+    // dynamic LDS of each pass launch (largest class that takes part)
+    size_t pass_lds[kMaxPass - 1] = {0, 0, 0}, last_lds = 0;
+    const size_t elem = prec == 1 ? 8 : 16;
+    for (int k = 0; k < ncls; ++k) {
+      const Plan& q = plans[k];
+      for (int ip = 0; ip + 1 < q.npass; ++ip) {
+        const FftPass& ps = q.pass[ip];
+        pass_lds[ip] = std::max(pass_lds[ip], elem * (size_t)(ps.L * ps.C + ps.L) + ps.L + 16);
+      }
+      const FftPass& ls = q.pass[q.npass - 1];
+      last_lds = std::max(last_lds, elem * (size_t)(ls.L * last_pitch(3 * ls.C) + ls.L));
+    }
+    // device layout: curves, plans, table pointers, works, items, status
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t o_cur = 0;
-    const size_t o_plan = o_cur + al(sizeof(BatchCurve) * ncurves);
-    const size_t o_tw = o_plan + al(sizeof(Plan) * ncls);
-    const size_t o_ph = o_tw + al(sizeof(void*) * ncls);
-    const size_t o_st = o_ph + al(sizeof(void*) * ncls);
-    const size_t o_cnt = o_st + al(sizeof(int) * ncurves);
-    const size_t dev_bytes = o_cnt + 256;
-    const size_t slot_bytes = layout_work(big, nd_max, 3, nullptr, nullptr);
-    const int nslots = (int)std::min<int64_t>(ncurves, 2 * (int64_t)ctx->num_cu);
-    const size_t ws_bytes = slot_bytes * nslots;
-    if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_bytes > ctx->budget)
+    size_t off = 0;
+    const size_t o_cur = off;
+    off += al(sizeof(BatchCurve) * ncurves);
+    const size_t o_plan = off;
+    off += al(sizeof(Plan) * ncls);
+    const size_t o_tw = off;
+    off += al(sizeof(void*) * ncls);
+    const size_t o_ph = off;
+    off += al(sizeof(void*) * ncls);
+    const size_t o_work = off;
+    off += al(sizeof(Work) * ncurves);
+    const size_t o_st = off;
+    off += al(sizeof(int) * ncurves);
+    std::vector<size_t> o_items(nchunks);
+    for (int k = 0; k < nchunks; ++k) {
+      o_items[k] = off;
+      size_t cnt = ci[k].spread.size() + ci[k].last.size();
+      for (int ip = 0; ip < kMaxPass - 1; ++ip) cnt += ci[k].pass[ip].size();
+      off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 1);
+    }
+    const size_t dev_bytes = off + 256;
+    if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_max > ctx->budget)
       return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
     he = hipStreamSynchronize(stream);
     if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
@@ -671,15 +713,15 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
       }
       B.dev_bytes = dev_bytes;
     }
-    if (B.ws_bytes < ws_bytes) {
+    if (B.ws_bytes < ws_max) {
       if (B.ws) (void)hipFree(B.ws);
       B.ws = nullptr;
       B.ws_bytes = 0;
-      if (hipMalloc(&B.ws, ws_bytes) != hipSuccess) {
+      if (hipMalloc(&B.ws, ws_max) != hipSuccess) {
         (void)hipGetLastError();
         return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch workspace failed");
       }
-      B.ws_bytes = ws_bytes;
+      B.ws_bytes = ws_max;
     }
     if (B.status_cap < (size_t)ncurves) {
       if (B.status_host) (void)hipHostFree(B.status_host);
@@ -688,59 +730,96 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
       if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "pinned status buffer");
       B.status_cap = ncurves;
     }
-    he = hipMemcpy(B.dev + o_cur, sorted.data(), sizeof(BatchCurve) * ncurves, hipMemcpyHostToDevice);
+    // workspaces of each chunk start at the base of the shared buffer
+    std::vector<Work> works(ncurves);
+    for (int k = 0; k < nchunks; ++k) {
+      size_t woff = 0;
+      for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
+        layout_work(plans[cls_of[c]], cur[c].nd, 3, B.ws + woff, &works[c], true);
+        woff += wsz[c];
+      }
+    }
+    he = hipMemcpy(B.dev + o_cur, cur.data(), sizeof(BatchCurve) * ncurves, hipMemcpyHostToDevice);
     if (he == hipSuccess)
       he = hipMemcpy(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls, hipMemcpyHostToDevice);
     if (he == hipSuccess)
       he = hipMemcpy(B.dev + o_tw, twp.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
     if (he == hipSuccess)
       he = hipMemcpy(B.dev + o_ph, php.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = hipMemcpy(B.dev + o_work, works.data(), sizeof(Work) * ncurves, hipMemcpyHostToDevice);
+    B.launches.assign(nchunks, BatchLaunch{});
+    for (int k = 0; k < nchunks && he == hipSuccess; ++k) {
+      BatchLaunch& L = B.launches[k];
+      const int64_t c0 = chunk_begin[k];
+      BatchArgs& ba = L.args;
+      ba.curves = reinterpret_cast<const BatchCurve*>(B.dev + o_cur) + c0;
+      ba.ncurves = (int)(chunk_begin[k + 1] - c0);
+      ba.plans = reinterpret_cast<const Plan*>(B.dev + o_plan);
+      ba.tw = reinterpret_cast<const void* const*>(B.dev + o_tw);
+      ba.inv_phihat = reinterpret_cast<const double* const*>(B.dev + o_ph);
+      ba.works = reinterpret_cast<const Work*>(B.dev + o_work) + c0;
+      ba.t = t;
+      ba.y = y;
+      ba.dy = dy;
+      ba.power = power;
+      ba.norm = common->normalization;
+      ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
+      ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
+      ba.status = reinterpret_cast<int*>(B.dev + o_st);
+      L.prec = prec;
+      size_t io = o_items[k];
+      auto put = [&](const std::vector<BatchItem>& v) -> const BatchItem* {
+        const BatchItem* ptr = reinterpret_cast<const BatchItem*>(B.dev + io);
+        if (!v.empty() && he == hipSuccess)
+          he = hipMemcpy(B.dev + io, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice);
+        io += al(sizeof(BatchItem) * v.size()) + 256;
+        return ptr;
+      };
+      L.spread_items = put(ci[k].spread);
+      L.nspread = (int)ci[k].spread.size();
+      for (int ip = 0; ip < kMaxPass - 1; ++ip) {
+        L.pass_items[ip] = put(ci[k].pass[ip]);
+        L.npass_items[ip] = (int)ci[k].pass[ip].size();
+        L.pass_lds[ip] = pass_lds[ip];
+      }
+      L.last_items = put(ci[k].last);
+      L.nlast = (int)ci[k].last.size();
+      L.last_lds = last_lds;
+    }
     if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
-    BatchArgs ba{};
-    ba.curves = reinterpret_cast<const BatchCurve*>(B.dev + o_cur);
-    ba.ncurves = (int)ncurves;
-    ba.plans = reinterpret_cast<const Plan*>(B.dev + o_plan);
-    ba.tw = reinterpret_cast<const void* const*>(B.dev + o_tw);
-    ba.inv_phihat = reinterpret_cast<const double* const*>(B.dev + o_ph);
-    ba.t = t;
-    ba.y = y;
-    ba.dy = dy;
-    ba.power = power;
-    ba.norm = common->normalization;
-    ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
-    ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
-    ba.counter = reinterpret_cast<unsigned int*>(B.dev + o_cnt);
-    ba.status = reinterpret_cast<int*>(B.dev + o_st);
-    layout_work(big, nd_max, 3, B.ws, &ba.w0);
-    ba.slot_stride = slot_bytes;
-    B.status_dev = ba.status;
+    B.status_dev = reinterpret_cast<int*>(B.dev + o_st);
     if (B.exec) (void)hipGraphExecDestroy(B.exec);
     if (B.graph) (void)hipGraphDestroy(B.graph);
     B.exec = nullptr;
     B.graph = nullptr;
-    B.args = ba;
-    B.nslots = nslots;
-    B.prec = prec;
     B.ncurves = ncurves;
     B.key = key;
     B.valid = true;
   }
+  auto launch_all = [&](hipStream_t s) -> hipError_t {
+    for (const BatchLaunch& L : B.launches) {
+      hipError_t e = launch_batch(L, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   if (use_graph && !B.exec) {
-    // capture the launch (queue reset + persistent kernel) once per batch layout
+    // capture the launches once per batch layout
     if (!B.cap_stream) {
       he = hipStreamCreateWithFlags(&B.cap_stream, hipStreamNonBlocking);
       if (he != hipSuccess) return hip_fail(ctx, he, "capture stream");
     }
     he = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
-      hipError_t le = launch_batch(B.args, B.nslots, B.prec, B.cap_stream);
+      hipError_t le = launch_all(B.cap_stream);
       he = hipStreamEndCapture(B.cap_stream, &B.graph);
       if (le != hipSuccess) he = le;
     }
     if (he == hipSuccess) he = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
     if (he != hipSuccess) return hip_fail(ctx, he, "batch graph capture");
   }
-  he = use_graph ? hipGraphLaunch(B.exec, stream) : launch_batch(B.args, B.nslots, B.prec, stream);
+  he = use_graph ? hipGraphLaunch(B.exec, stream) : launch_all(stream);
   if (he == hipSuccess)
     he = hipMemcpyAsync(B.status_host, B.status_dev, sizeof(int32_t) * ncurves,
                         hipMemcpyDeviceToHost, stream);

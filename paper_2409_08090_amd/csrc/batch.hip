@@ -1,13 +1,14 @@
-// batch.hip -- periodograms of many independent series in one persistent
-// launch (gfx950).
+// batch.hip -- periodograms of many independent series (gfx950).
 //
-// A fixed number of workgroups (slots, ~2 per CU) each own a private
-// workspace; a workgroup takes the next series from an atomic queue (ordered
-// by decreasing cost on the host), runs the whole path for it -- statistics,
-// binning, both spreads, every FFT pass and the fused deconvolution/power --
-// with barriers between phases, and moves on.  No workgroup ever waits for
-// another, so the launch always drains.  Series are grouped into grid-size
-// classes that share a plan (twiddles, kernel transform).
+// A batch runs as a short sequence of launches (captured once in a HIP graph
+// by the host): one workgroup per series computes its statistics, binning
+// and direct low-frequency sums; then each later phase -- both spreads, every
+// FFT pass, the last pass with deconvolution and power -- is one launch whose
+// workgroups are the tiles of all series of the batch (a host-built work
+// list of (series, tile) items), so that every phase has the whole GPU's
+// memory parallelism whatever the size mix.  Series are grouped into
+// grid-size classes that share a plan (twiddles, kernel transform); each
+// series has its own workspace.
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -174,18 +175,9 @@ __device__ void bins_block(const CallArgs& a, const Plan& p, const Work& w, DevS
   __syncthreads();
 }
 
-__device__ __noinline__ void batch_stats(const CallArgs& a, DevStats* st, double* sh, int* shi) {
-  stats_block(a, st, sh, shi);
-}
-__device__ __noinline__ void batch_bins(const CallArgs& a, const Plan& p, const Work& w,
-                                        DevStats* st, int* shi) {
-  bins_block(a, p, w, st, shi);
-}
-
 // Direct FP64 sums near f = 0 for one series (see k_lowfreq): lowfix gets
 // kLowMax x 6 values, st->k_lo / st->nlow the frequencies they belong to.
-__device__ __noinline__ void batch_lowfreq(const CallArgs& a, DevStats* st, double* lowfix,
-                                           double* red) {
+__device__ void lowfreq_block(const CallArgs& a, DevStats* st, double* lowfix, double* red) {
   const DevStats& s = *st;
   int64_t k_lo;
   int nlow;
@@ -204,200 +196,170 @@ __device__ __noinline__ void batch_lowfreq(const CallArgs& a, DevStats* st, doub
   __syncthreads();
 }
 
-__device__ __forceinline__ void block_fence() {
-  __threadfence();
-  __syncthreads();
+__device__ __forceinline__ CallArgs curve_args(const BatchArgs& ba, const BatchCurve& c) {
+  CallArgs a{};
+  a.t = ba.t + c.t_off;
+  a.y = ba.y + c.t_off;
+  a.dy = ba.dy ? ba.dy + c.t_off : nullptr;
+  a.nd = c.nd;
+  a.nf = c.nf;
+  a.f0 = c.f0;
+  a.df = c.df;
+  a.fch = c.fch;
+  a.fcl = c.fcl;
+  a.kzero = c.kzero;
+  a.norm = ba.norm;
+  a.center = ba.center;
+  a.fit_mean = ba.fit_mean;
+  a.periodogram = 1;
+  a.power = ba.power + c.out_off;
+  return a;
 }
 
-// Phase wrappers kept out of line: each phase gets its own register
-// allocation instead of the union of all of them.
-// A batched series spreads tiles of several whole rows, up to what the
-// dynamic LDS holds for geometry f (two grids), to amortise the per-tile cost.
-template <typename Real>
-__device__ __forceinline__ int batch_tile_cells() {
-  return kBatchLds / (2 * 2 * (int)sizeof(Real));
+// Copy of a series' plan into LDS (it is read often and is the same for the
+// whole workgroup).
+__device__ __forceinline__ void load_plan(const Plan* src, Plan* dst) {
+  const int* s = reinterpret_cast<const int*>(src);
+  int* d = reinterpret_cast<int*>(dst);
+  for (int i = threadIdx.x; i < (int)(sizeof(Plan) / sizeof(int)); i += blockDim.x) d[i] = s[i];
 }
-template <typename Real>
-__device__ __forceinline__ int batch_tile(const Plan& p) {
-  const int cap = batch_tile_cells<Real>();
-  return p.S1 <= cap ? (int)(p.S1 * (cap / p.S1)) : p.T;
+
+// Per-series prologue: one workgroup per series.
+__global__ __launch_bounds__(NT) void k_bpro(BatchArgs ba) {
+  __shared__ double sh[5 * NT];
+  __shared__ int shi[2 * NT + 2];
+  __shared__ Plan sp;
+  const int ci = blockIdx.x;
+  const BatchCurve c = ba.curves[ci];
+  load_plan(ba.plans + c.plan, &sp);
+  __syncthreads();
+  const CallArgs a = curve_args(ba, c);
+  const Work w = ba.works[ci];
+  stats_block(a, w.stats, sh, shi);
+  if (w.stats->status != 0) {
+    if (threadIdx.x == 0) ba.status[c.index] = w.stats->status;
+    return;
+  }
+  bins_block(a, sp, w, w.stats, shi);
+  lowfreq_block(a, w.stats, w.lowfix, sh);
+  // row flags of both geometries, so that the spread's workgroups of empty
+  // rows stop at once
+  const int h = (int)ceil(sp.hw) + 1;
+  for (int r = threadIdx.x; r < (int)sp.nrows; r += NT) {
+    w.rowflag_f[r] = (unsigned char)row_active<1>(r, h, sp, w.bin_start, (int)a.nd);
+    w.rowflag_2f[r] = (unsigned char)row_active<2>(r, h, sp, w.bin_start, (int)a.nd);
+  }
+  if (threadIdx.x == 0) ba.status[c.index] = 0;
 }
-template <typename Real>
-__device__ __noinline__ void batch_spread_f(int tile, int Tt, const CallArgs& a, const Plan& p,
-                                            const Work& w, const DevStats& st,
-                                            unsigned char* smem, int* rb, int* re, int* sv) {
-  spread_tile<Real, 1, 2, NT>(tile, Tt, batch_tile_cells<Real>(), a, p, w, st, 0, w.rowflag_f,
-                              reinterpret_cast<Real*>(smem), rb, re, sv);
+
+// Spreading: one workgroup per tile of one series (every tile of every
+// series; tiles of rows no kernel support reaches only write their flag).
+// The row flags come from the prologue: a tile of an empty row returns after
+// one flag read.
+template <typename Real, int GEO, int NG>
+__global__ __launch_bounds__(NT) void k_bspread(BatchArgs ba, const BatchItem* items) {
+  __shared__ Real acc[NG * 2 * kTileMax];
+  __shared__ int rb[8], re[8], sv[2];
+  __shared__ Plan sp;
+  const BatchItem it = items[blockIdx.x];
+  const BatchCurve c = ba.curves[it.curve];
+  const Work& w = ba.works[it.curve];
+  const Plan* pl = ba.plans + c.plan;
+  const int row = (int)(((int64_t)it.sub * pl->T) / pl->S1);
+  if ((GEO == 1 ? w.rowflag_f : w.rowflag_2f)[row] == 0) return;
+  const DevStats st = *w.stats;
+  if (st.status != 0) return;
+  load_plan(pl, &sp);
+  __syncthreads();
+  const CallArgs a = curve_args(ba, c);
+  spread_tile<Real, GEO, NG, NT, true>(it.sub, sp.T, kTileMax, a, sp, w, st, GEO == 1 ? 0 : 2,
+                                       nullptr, acc, rb, re, sv);
 }
+
+// A first/middle FFT pass ip: one workgroup per (series, grid, column block).
+// Pass 0 works in place on grid; later passes alternate grid -> grid2 -> grid.
 template <typename Real>
-__device__ __noinline__ void batch_spread_2f(int tile, int Tt, const CallArgs& a, const Plan& p,
-                                             const Work& w, const DevStats& st,
-                                             unsigned char* smem, int* rb, int* re, int* sv) {
-  spread_tile<Real, 2, 1, NT>(tile, Tt, batch_tile_cells<Real>(), a, p, w, st, 2, w.rowflag_2f,
-                              reinterpret_cast<Real*>(smem), rb, re, sv);
-}
-template <typename Real>
-__device__ __forceinline__ void batch_pass(int64_t blk, const typename cplx<Real>::T* in,
-                                        typename cplx<Real>::T* out, const unsigned char* rf,
-                                        const FftPass& ps, const typename cplx<Real>::T* tw,
-                                        unsigned char* smem) {
-  constexpr int EMID = sizeof(Real) == 8 ? kEmid64 : kEmid32;
-  fft_pass_block<Real, EMID, NT>(blk, in, out, rf, ps, tw, smem);
-}
-template <typename Real>
-__device__ __forceinline__ void batch_last(int64_t blk, void* const* grids, const FftPass& ps,
-                                        int64_t n, int64_t nf, int64_t K, const CallArgs& a,
-                                        const typename cplx<Real>::T* tw, const double* iph,
-                                        const DevStats& st, unsigned char* smem,
-                                        const double* lowfix) {
+__global__ __launch_bounds__(NT) void k_bpass(BatchArgs ba, const BatchItem* items, int ip) {
   using T2 = typename cplx<Real>::T;
-  constexpr int ELAST = sizeof(Real) == 8 ? kElastBatch64 : kElastBatch32;
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int EMID = sizeof(Real) == 8 ? kEmid64 : kEmid32;
+  __shared__ FftPass ps;  // in LDS: its radix list is indexed at run time
+  const BatchItem it = items[blockIdx.x];
+  const Work& w = ba.works[it.curve];  // in place: grid[g] is indexed at run time
+  if (w.stats->status != 0) return;
+  const int cls = ba.curves[it.curve].plan;
+  {
+    const int* src = reinterpret_cast<const int*>(&ba.plans[cls].pass[ip]);
+    int* dst = reinterpret_cast<int*>(&ps);
+    for (int i = threadIdx.x; i < (int)(sizeof(FftPass) / sizeof(int)); i += NT) dst[i] = src[i];
+  }
+  __syncthreads();
+  const int nblk = (int)(ps.P * ((ps.S + ps.C - 1) / ps.C));
+  const int g = it.sub / nblk;
+  const int blk = it.sub - g * nblk;
+  T2* gr = reinterpret_cast<T2*>(w.grid[g]);
+  T2* g2 = reinterpret_cast<T2*>(w.grid2[g]);
+  const T2* in = (ip == 0 || ip % 2 == 1) ? gr : g2;
+  T2* out = ip == 0 ? gr : (ip % 2 == 1 ? g2 : gr);
+  const unsigned char* rf = ip == 0 ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
+  fft_pass_block<Real, EMID, NT>(blk, in, out, rf, ps, reinterpret_cast<const T2*>(ba.tw[cls]),
+                                 smem);
+}
+
+// The last pass with deconvolution, crop and power: one workgroup per
+// (series, row block).
+template <typename Real>
+__global__ __launch_bounds__(kThreadsLast) void k_blast(BatchArgs ba, const BatchItem* items) {
+  using T2 = typename cplx<Real>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int ELAST = sizeof(Real) == 8 ? kElast64 : kElast32;
+  const BatchItem it = items[blockIdx.x];
+  const BatchCurve c = ba.curves[it.curve];
+  const Work w = ba.works[it.curve];
+  const DevStats st = *w.stats;
+  if (st.status != 0) return;
+  // no static LDS here: the dynamic part may use all 64 KB
+  const Plan* pl = ba.plans + c.plan;
+  const int npass = pl->npass;
+  const int64_t n = pl->n;
+  const FftPass& ps = pl->pass[npass - 1];  // read in place (its radix list is indexed at run time)
+  const CallArgs a = curve_args(ba, c);
+  const bool in2 = npass >= 3 && ((npass - 2) % 2 == 1);
   PassBufs<Real> b;
   for (int g = 0; g < 3; ++g) {
-    b.in[g] = reinterpret_cast<T2*>(grids[g]);
+    b.in[g] = reinterpret_cast<T2*>(in2 ? w.grid2[g] : w.grid[g]);
     b.out[g] = nullptr;
     b.rowflag[g] = nullptr;
   }
-  fft_last_block<Real, 3, ELAST, NT>(blk, b, ps, n, nf, K, a, tw, iph, st, smem, lowfix);
+  fft_last_block<Real, 3, ELAST, kThreadsLast>(it.sub, b, ps, n, c.nf, c.K, a,
+                                               reinterpret_cast<const T2*>(ba.tw[c.plan]),
+                                               ba.inv_phihat[c.plan], st, smem, w.lowfix, 1);
 }
 
 template <typename Real>
-__global__ __launch_bounds__(NT, 2) void k_batch(BatchArgs ba) {
-  using T2 = typename cplx<Real>::T;
-  extern __shared__ __align__(16) unsigned char smem[];
-  // per-series state lives in LDS, not in registers, across the phases
-  __shared__ Plan sp;
-  __shared__ CallArgs sa;
-  __shared__ Work sw;
-  __shared__ DevStats sst;
-  __shared__ BatchCurve sc;
-  __shared__ int s_cur;
-  __shared__ int rb[8], re[8], sv[2];
-  __shared__ int shi[2 * NT + 2];
-  __shared__ double slow[6 * kLowMax];
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    // this slot's workspace
-    Work w = ba.w0;
-    const size_t off = (size_t)blockIdx.x * ba.slot_stride;
-    auto sh = [&](auto* ptr) {
-      return ptr ? reinterpret_cast<decltype(ptr)>(reinterpret_cast<char*>(ptr) + off) : ptr;
-    };
-    w.stats = sh(w.stats);
-    w.partials = sh(w.partials);
-    w.bin_start = sh(w.bin_start);
-    w.bin_count = sh(w.bin_count);
-    w.bin_cursor = sh(w.bin_cursor);
-    w.scan_part = sh(w.scan_part);
-    w.ts = sh(w.ts);
-    w.ys = sh(w.ys);
-    w.dys = sh(w.dys);
-    w.rowflag_f = sh(w.rowflag_f);
-    w.rowflag_2f = sh(w.rowflag_2f);
-    for (int g = 0; g < 3; ++g) {
-      w.grid[g] = sh(reinterpret_cast<char*>(w.grid[g]));
-      w.grid2[g] = sh(reinterpret_cast<char*>(w.grid2[g]));
-    }
-    sw = w;
+hipError_t launch_t(const BatchLaunch& bl, hipStream_t s) {
+  const BatchArgs& ba = bl.args;
+  hipLaunchKernelGGL(k_bpro, dim3(ba.ncurves), dim3(NT), 0, s, ba);
+  if (bl.nspread > 0) {
+    hipLaunchKernelGGL((k_bspread<Real, 1, 2>), dim3(bl.nspread), dim3(NT), 0, s, ba,
+                       bl.spread_items);
+    hipLaunchKernelGGL((k_bspread<Real, 2, 1>), dim3(bl.nspread), dim3(NT), 0, s, ba,
+                       bl.spread_items);
   }
-  for (;;) {
-    if (tid == 0) s_cur = (int)atomicAdd(ba.counter, 1u);
-    __syncthreads();
-    const int ci = s_cur;
-    if (ci >= ba.ncurves) break;
-    {
-      const int* src = reinterpret_cast<const int*>(ba.plans + ba.curves[ci].plan);
-      int* dst = reinterpret_cast<int*>(&sp);
-      for (int i = tid; i < (int)(sizeof(Plan) / sizeof(int)); i += NT) dst[i] = src[i];
-    }
-    if (tid == 0) {
-      const BatchCurve c = ba.curves[ci];
-      sc = c;
-      CallArgs a{};
-      a.t = ba.t + c.t_off;
-      a.y = ba.y + c.t_off;
-      a.dy = ba.dy ? ba.dy + c.t_off : nullptr;
-      a.nd = c.nd;
-      a.nf = c.nf;
-      a.f0 = c.f0;
-      a.df = c.df;
-      a.fch = c.fch;
-      a.fcl = c.fcl;
-      a.kzero = c.kzero;
-      a.norm = ba.norm;
-      a.center = ba.center;
-      a.fit_mean = ba.fit_mean;
-      a.periodogram = 1;
-      a.power = ba.power + c.out_off;
-      sa = a;
-    }
-    __syncthreads();
-    const Plan& p = sp;
-    const CallArgs& a = sa;
-    const Work& w = sw;
-    batch_stats(a, w.stats, reinterpret_cast<double*>(smem), shi);
-    if (w.stats->status != 0) {
-      if (tid == 0) ba.status[sc.index] = w.stats->status;
-      __syncthreads();
-      continue;
-    }
-    batch_bins(a, p, w, w.stats, shi);
-    batch_lowfreq(a, w.stats, slow, reinterpret_cast<double*>(smem));
-    if (tid == 0) sst = *w.stats;
-    __syncthreads();
-    const DevStats& sts = sst;
-    const T2* tw = reinterpret_cast<const T2*>(ba.tw[sc.plan]);
-    const double* iph = ba.inv_phihat[sc.plan];
-    // spreads
-    const int Tt = batch_tile<Real>(p);
-    const int ntiles = (int)((p.n + Tt - 1) / Tt);
-    for (int tile = 0; tile < ntiles; ++tile)
-      batch_spread_f<Real>(tile, Tt, a, p, w, sts, smem, rb, re, sv);
-    for (int tile = 0; tile < ntiles; ++tile)
-      batch_spread_2f<Real>(tile, Tt, a, p, w, sts, smem, rb, re, sv);
-    block_fence();
-    // FFT passes: pass 0 in place on grid, then grid -> grid2 -> grid ...
-    const int npass = p.npass;
-    for (int ip = 0; ip + 1 < npass; ++ip) {
-      const FftPass& ps = p.pass[ip];
-      const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-      for (int g = 0; g < 3; ++g) {
-        T2* gr = reinterpret_cast<T2*>(w.grid[g]);
-        T2* g2 = reinterpret_cast<T2*>(w.grid2[g]);
-        const T2* in = (ip == 0 || ip % 2 == 1) ? gr : g2;
-        T2* out = ip == 0 ? gr : (ip % 2 == 1 ? g2 : gr);
-        const unsigned char* rf = ip == 0 ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
-        for (int64_t blk = 0; blk < nblk; ++blk) batch_pass<Real>(blk, in, out, rf, ps, tw, smem);
-      }
-      block_fence();
-    }
-    {
-      // the last pass reads grid2 after an odd number of out-of-place passes
-      const bool in2 = npass >= 3 && ((npass - 2) % 2 == 1);
-      const FftPass& ps = p.pass[npass - 1];
-      const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
-      for (int64_t blk = 0; blk < nblk; ++blk)
-        batch_last<Real>(blk, in2 ? w.grid2 : w.grid, ps, p.n, sc.nf, sc.K, a, tw, iph, sts, smem,
-                         slow);
-    }
-    if (tid == 0) ba.status[sc.index] = 0;
-    block_fence();
-  }
-}
-
-__global__ void k_batch_reset(unsigned int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+  for (int ip = 0; ip < kMaxPass - 1; ++ip)
+    if (bl.npass_items[ip] > 0)
+      hipLaunchKernelGGL(k_bpass<Real>, dim3(bl.npass_items[ip]), dim3(NT), bl.pass_lds[ip], s,
+                         ba, bl.pass_items[ip], ip);
+  if (bl.nlast > 0)
+    hipLaunchKernelGGL(k_blast<Real>, dim3(bl.nlast), dim3(kThreadsLast), bl.last_lds, s, ba,
+                       bl.last_items);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_batch(const BatchArgs& ba, int nslots, int prec, hipStream_t s) {
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, ba.counter);
-  if (prec == 1)
-    hipLaunchKernelGGL(k_batch<float>, dim3(nslots), dim3(NT), kBatchLds, s, ba);
-  else
-    hipLaunchKernelGGL(k_batch<double>, dim3(nslots), dim3(NT), kBatchLds, s, ba);
-  return hipGetLastError();
+hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
+  return bl.prec == 1 ? launch_t<float>(bl, s) : launch_t<double>(bl, s);
 }
 
 }  // namespace mils

@@ -143,8 +143,6 @@ constexpr int kLmax = 1024;         // longest per-pass FFT length
 constexpr int kEmid64 = 2048, kEmid32 = 4096;
 constexpr int kElast64 = 3072, kElast32 = 6144;
 // the persistent batched kernel runs every phase with 256 threads
-constexpr int kElastBatch64 = 1536, kElastBatch32 = 3072;
-constexpr int kBatchLds = 65536;    // dynamic LDS of the batched kernel
 // Near f = 0 (|f| * span < 2) the floating-mean terms CC = (1 + C2)/2 - C^2 etc.
 // cancel and the 2x2 fit is ill-conditioned; there the three sums are
 // evaluated directly (FP64, at most kLowMax frequencies) instead of read

@@ -199,9 +199,8 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   nmin = std::max<int64_t>(nmin, 16);
   const int G = r.G;
   const int emid = r.prec == 1 ? kEmid32 : kEmid64;
-  const int elast = r.batch ? (r.prec == 1 ? kElastBatch32 : kElastBatch64)
-                            : (r.prec == 1 ? kElast32 : kElast64);
-  const int dmin = r.batch ? 1 : 4;
+  const int elast = r.prec == 1 ? kElast32 : kElast64;
+  const int dmin = 4;
   const int cmax = 32;
 
   std::vector<int64_t> cand = r.n_fixed > 0 ? std::vector<int64_t>{r.n_fixed}
@@ -458,7 +457,7 @@ void phihat_nodes(const Plan& p, std::vector<double>* z, std::vector<double>* gp
   }
 }
 
-size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
+size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w, bool per_series) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     off = (off + 255) & ~(size_t)255;
@@ -468,7 +467,7 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
   };
   Work x{};
   x.stats = reinterpret_cast<DevStats*>(take(sizeof(DevStats)));
-  x.partials = reinterpret_cast<double*>(take(sizeof(double) * 8 * kStatsBlocks));
+  if (!per_series) x.partials = reinterpret_cast<double*>(take(sizeof(double) * 8 * kStatsBlocks));
   x.bin_start = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
   x.bin_count = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
   x.bin_cursor = reinterpret_cast<int*>(take(sizeof(int) * (p.nbins + 1)));
@@ -481,13 +480,15 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w) {
   } else {
     x.hs = reinterpret_cast<double*>(take(sizeof(double) * nd));
   }
-  x.lowpart = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowBlocks));
-  x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowParts));
+  if (!per_series) x.lowpart = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowBlocks));
+  x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * (per_series ? 1 : kLowParts)));
   x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));
-  x.act_rows_f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
-  x.act_rows_2f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
-  x.nact = reinterpret_cast<int*>(take(sizeof(int) * 2));
+  if (!per_series) {
+    x.act_rows_f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
+    x.act_rows_2f = reinterpret_cast<int*>(take(sizeof(int) * p.nrows));
+    x.nact = reinterpret_cast<int*>(take(sizeof(int) * 2));
+  }
   const size_t cbytes = p.prec == 1 ? 8 : 16;
   for (int g = 0; g < G; ++g) x.grid[g] = take(cbytes * p.n);
   if (p.npass >= 3)

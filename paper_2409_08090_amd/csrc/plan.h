@@ -18,7 +18,7 @@ struct PlanRequest {
   int prec;             // 0 FP64, 1 FP32
   int G;                // grids transformed together in the last pass (3 or 1)
   double sigma = 0.0;   // upsampling factor; 0 = the precision's default
-  bool batch = false;   // plan for the persistent batched kernel (256-thread last pass)
+  bool batch = false;   // plan for the batched kernels (no big passes)
   int64_t n_fixed = 0;  // use exactly this grid size (must factor), 0 = choose
 };
 
@@ -50,6 +50,10 @@ void make_horner(const Plan& p, std::vector<double>* coef);
 
 // Device workspace layout of one call; returns the byte size.  With base ==
 // nullptr only the size is computed.
-size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w);
+// Workspace of one call (nd points, G grids) at base (nullptr: size only).
+// per_series: the workspace of one series of a batch, without the buffers of
+// the multi-workgroup reductions of the single-series path.
+size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w,
+                   bool per_series = false);
 
 }  // namespace mils

@@ -5,8 +5,8 @@
 // state) and pinned staging buffers, and runs in its own thread: when it is
 // free it takes every compatible request that has arrived (same precision,
 // tolerance, normalisation and flags), as far as the HBM budget allows, packs
-// them into one batch, runs the persistent batched kernel on its stream and
-// copies the results back.  While one lane's batch is on the device, the next
+// them into one batch, runs the batched launches on its stream and copies the
+// results back.  While one lane's batch is on the device, the next
 // arrivals are packed by another lane, so batches overlap on the GPU.
 // Requests with many frequencies run through the single-series path instead.
 #include <hip/hip_runtime.h>
@@ -31,10 +31,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Above this many frequencies a request uses the single-series path: a
-// batched series is handled by one workgroup, whose private workspace would
-// otherwise grow with the largest grid of the batch.
-constexpr int64_t kBatchMaxNf = 60000;
+// Above this many frequencies a request uses the single-series path: its
+// own grids fill the GPU, and batching it would only hold back the small
+// requests packed with it.
+constexpr int64_t kBatchMaxNf = 200000;
 
 struct Request {
   std::vector<double> t, y, dy;
