@@ -202,6 +202,19 @@ int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd
                            const mils_params *common, double *power,
                            int32_t *status_per_curve, void *hip_stream);
 
+/* The batch autotuner's decision for series of nf frequencies at (eps,
+ * precision): the first mils_periodogram_batch call on a context times, for
+ * every half-octave band of N_f holding at least 16 of its series, a sample of
+ * them under a few upsampling factors sigma (0 stands for the planner's own
+ * choice; larger sigma: a wider grid with a narrower kernel) and largest
+ * spreading tiles, and keeps the fastest for later batches of the context
+ * (Sec. 2 of the paper sets the grid and the kernel width from eps; which
+ * admissible pair is fastest depends on the size).  Returns MILS_OK with
+ * *sigma and *tile_max set, or MILS_ERR_INVALID_ARG when the band has no
+ * decision.  Setting MILS_AUTOTUNE=0 in the environment turns the tuner off. */
+int mils_batch_tuning(mils_context *ctx, int64_t nf, double eps, int32_t precision,
+                      double *sigma, int32_t *tile_max);
+
 /*
  * Serving loop: requests of mixed sizes and precisions are submitted from host
  * memory, admitted while the device memory they need fits the HBM budget,

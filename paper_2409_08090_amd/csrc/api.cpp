@@ -32,7 +32,7 @@ struct PlanEntry {
 };
 
 // (nf, eps, precision, grids + 10 * batch, fixed grid size)
-using PlanKey = std::tuple<int64_t, double, int, int, int64_t>;
+using PlanKey = std::tuple<int64_t, double, int, int, int64_t, int>;
 
 std::mutex g_err_mu;
 std::string g_create_err;
@@ -96,8 +96,19 @@ struct BatchState {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  std::map<std::tuple<int64_t, int, double>, int64_t> grid_of_nf;  // (nf, prec, eps) -> grid size
+  // (nf, prec, eps, sigma) -> grid size
+  std::map<std::tuple<int64_t, int, double, double>, int64_t> grid_of_nf;
 };
+
+void free_batch_state(BatchState& b) {
+  if (b.exec) (void)hipGraphExecDestroy(b.exec);
+  if (b.graph) (void)hipGraphDestroy(b.graph);
+  if (b.cap_stream) (void)hipStreamDestroy(b.cap_stream);
+  if (b.dev) (void)hipFree(b.dev);
+  if (b.ws) (void)hipFree(b.ws);
+  if (b.status_host) (void)hipHostFree(b.status_host);
+  b = BatchState{};
+}
 
 }  // namespace
 
@@ -121,6 +132,8 @@ struct mils_context {
   std::vector<hipEvent_t> prof_pool;
   int num_cu = 256;
   BatchState batch;
+  // batch autotuner: (N_f band, eps, precision) -> (sigma, largest spreading tile)
+  std::map<std::tuple<int, double, int>, std::pair<double, int>> tuned;
 };
 
 namespace {
@@ -160,8 +173,8 @@ int check_nd(int64_t nd) {
 }
 
 int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEntry** out,
-             bool upload, bool batch = false, int64_t n_fixed = 0) {
-  PlanKey key{nf, eps, prec, G + (batch ? 10 : 0), n_fixed};
+             bool upload, bool batch = false, int64_t n_fixed = 0, int tile_max = 0) {
+  PlanKey key{nf, eps, prec, G + (batch ? 10 : 0), n_fixed, tile_max};
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end() && (!upload || it->second.tw)) {
     *out = &it->second;
@@ -172,6 +185,7 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   PlanRequest r{nf, eps, prec, G};
   r.batch = batch;
   r.n_fixed = n_fixed;
+  r.tile_max = tile_max;
   if (!make_plan(r, &e.plan, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
   std::vector<double> tw;
   make_twiddles(&e.plan, &tw);
@@ -399,13 +413,7 @@ int mils_context_destroy(mils_context* ctx) {
     for (auto& kv : ctx->plans)
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
-    BatchState& b = ctx->batch;
-    if (b.exec) (void)hipGraphExecDestroy(b.exec);
-    if (b.graph) (void)hipGraphDestroy(b.graph);
-    if (b.cap_stream) (void)hipStreamDestroy(b.cap_stream);
-    if (b.dev) (void)hipFree(b.dev);
-    if (b.ws) (void)hipFree(b.ws);
-    if (b.status_host) (void)hipHostFree(b.status_host);
+    free_batch_state(ctx->batch);
     if (ctx->host_status) (void)hipHostFree(ctx->host_status);
     for (auto& r : ctx->prof_recs) {
       (void)hipEventDestroy(std::get<1>(r));
@@ -521,6 +529,354 @@ int mils_check_params(const mils_params* p, int64_t nd) {
 
 // Body of mils_periodogram_batch; the serving loop calls it with
 // use_graph = false (its batches change with every call).
+// Builds the launches of a batch in B: the series idx[0..m) (indices into the
+// caller's arrays, which keep their offsets and output positions), series i
+// planned with upsampling factor sig[i] (0: the planner's choice) and
+// spreading tiles of at most tmax[i] cells.  nstatus: size of the status array
+// (the caller's number of series).
+int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& idx,
+                const std::vector<double>& sig, const std::vector<int>& tmax,
+                const int64_t* nd_off, const double* t, const double* y, const double* dy,
+                const int64_t* nf_off, const double* f0, const double* df,
+                const mils_params* common, double* power, int64_t nstatus, hipStream_t stream) {
+  const int64_t m = (int64_t)idx.size();
+  const int prec = common->precision;
+  hipError_t he = hipSuccess;
+  // grid size of each series, then grid-size classes (ratio <= 1.06) that share a plan
+  std::vector<int64_t> ngrid(m);
+  for (int64_t c = 0; c < m; ++c) {
+    const int64_t nf = nf_off[idx[c] + 1] - nf_off[idx[c]];
+    auto k = std::make_tuple(nf, prec, common->eps, sig[c]);
+    auto it = B.grid_of_nf.find(k);
+    if (it == B.grid_of_nf.end()) {
+      Plan pl;
+      std::string err;
+      PlanRequest r{nf, common->eps, prec, 3};
+      r.batch = true;
+      r.sigma = sig[c];
+      if (!make_plan(r, &pl, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
+      it = B.grid_of_nf.emplace(k, pl.n).first;
+    }
+    ngrid[c] = it->second;
+  }
+  std::vector<std::pair<int64_t, int>> ns(m);
+  for (int64_t c = 0; c < m; ++c) ns[c] = {ngrid[c], tmax[c]};
+  std::sort(ns.begin(), ns.end(), [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) {
+    return x.second != y.second ? x.second < y.second : x.first < y.first;
+  });
+  ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+  // classes are keyed by (grid size, tile cap)
+  std::map<std::pair<int64_t, int>, int> cls_of_n;
+  std::vector<int64_t> cls_n;
+  std::vector<int> cls_t;
+  for (size_t i = 0; i < ns.size();) {
+    size_t j = i;
+    while (j + 1 < ns.size() && ns[j + 1].second == ns[i].second &&
+           (double)ns[j + 1].first <= 1.06 * (double)ns[i].first)
+      ++j;
+    const int cid = (int)cls_n.size();
+    cls_n.push_back(ns[j].first);
+    cls_t.push_back(ns[i].second);
+    for (size_t q = i; q <= j; ++q) cls_of_n[ns[q]] = cid;
+    i = j + 1;
+  }
+  const int ncls = (int)cls_n.size();
+  std::vector<int64_t> cls_nf(ncls, 1);
+  std::vector<int> cls_of(m);
+  for (int64_t c = 0; c < m; ++c) {
+    cls_of[c] = cls_of_n[{ngrid[c], tmax[c]}];
+    cls_nf[cls_of[c]] = std::max<int64_t>(cls_nf[cls_of[c]], nf_off[idx[c] + 1] - nf_off[idx[c]]);
+  }
+  std::vector<Plan> plans(ncls);
+  std::vector<const void*> twp(ncls);
+  std::vector<const double*> php(ncls);
+  for (int k = 0; k < ncls; ++k) {
+    PlanEntry* pe = nullptr;
+    int rc = get_plan(ctx, cls_nf[k], common->eps, prec, 3, &pe, true, true, cls_n[k], cls_t[k]);
+    if (rc != MILS_OK) return rc;
+    plans[k] = pe->plan;
+    twp[k] = pe->tw;
+    php[k] = pe->inv_phihat;
+  }
+  // series descriptors and their workspaces; chunks whose workspaces fit the cap
+  std::vector<BatchCurve> cur(m);
+  std::vector<size_t> wsz(m);
+  for (int64_t c = 0; c < m; ++c) {
+    const int64_t oc = idx[c];
+    BatchCurve& d = cur[c];
+    d.t_off = nd_off[oc];
+    d.nd = nd_off[oc + 1] - nd_off[oc];
+    d.out_off = nf_off[oc];
+    d.nf = nf_off[oc + 1] - nf_off[oc];
+    d.K = d.nf / 2;
+    d.f0 = f0[oc];
+    d.df = df[oc];
+    centre_frequency(d.f0, d.df, d.K, &d.fch, &d.fcl);
+    d.kzero = zero_index(d.f0, d.df, d.nf);
+    d.plan = cls_of[c];
+    d.index = (int)oc;
+    wsz[c] = (layout_work(plans[cls_of[c]], d.nd, 3, nullptr, nullptr, true) + 255) & ~(size_t)255;
+  }
+  size_t cap = kBatchWorkspaceCap;
+  if (ctx->budget) {
+    const size_t used = ctx->plan_bytes + ctx->ws_bytes;
+    cap = ctx->budget > used ? std::min<size_t>(cap, (ctx->budget - used) / 2) : 0;
+  }
+  std::vector<int64_t> chunk_begin{0};
+  size_t acc = 0, ws_max = 0;
+  for (int64_t c = 0; c < m; ++c) {
+    if (wsz[c] > cap) return fail(ctx, MILS_ERR_OOM, "a series of the batch exceeds the HBM budget");
+    if (acc + wsz[c] > cap) {
+      chunk_begin.push_back(c);
+      ws_max = std::max(ws_max, acc);
+      acc = 0;
+    }
+    acc += wsz[c];
+  }
+  ws_max = std::max(ws_max, acc);
+  chunk_begin.push_back(m);
+  const int nchunks = (int)chunk_begin.size() - 1;
+  // work items of every chunk
+  struct ChunkItems {
+    std::vector<BatchItem> spread, pass[kMaxPass - 1], last;
+  };
+  std::vector<ChunkItems> ci(nchunks);
+  for (int k = 0; k < nchunks; ++k) {
+    for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
+      const Plan& q = plans[cls_of[c]];
+      const int lc = (int)(c - chunk_begin[k]);
+      for (int64_t tl = 0; tl < q.n / q.T; ++tl) ci[k].spread.push_back({lc, (int)tl});
+      for (int ip = 0; ip + 1 < q.npass; ++ip) {
+        const FftPass& ps = q.pass[ip];
+        const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
+        for (int64_t x = 0; x < 3 * nblk; ++x) ci[k].pass[ip].push_back({lc, (int)x});
+      }
+      const FftPass& ls = q.pass[q.npass - 1];
+      for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x});
+    }
+  }
+  // dynamic LDS of each pass launch (largest class that takes part)
+  size_t pass_lds[kMaxPass - 1] = {0, 0, 0}, last_lds = 0;
+  const size_t elem = prec == 1 ? 8 : 16;
+  for (int k = 0; k < ncls; ++k) {
+    const Plan& q = plans[k];
+    for (int ip = 0; ip + 1 < q.npass; ++ip) {
+      const FftPass& ps = q.pass[ip];
+      pass_lds[ip] = std::max(pass_lds[ip], elem * (size_t)(ps.L * ps.C + ps.L) + ps.L + 16);
+    }
+    const FftPass& ls = q.pass[q.npass - 1];
+    last_lds = std::max(last_lds, elem * (size_t)(ls.L * last_pitch(3 * ls.C) + ls.L));
+  }
+  // device layout: curves, plans, table pointers, works, items, status
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t off = 0;
+  const size_t o_cur = off;
+  off += al(sizeof(BatchCurve) * m);
+  const size_t o_plan = off;
+  off += al(sizeof(Plan) * ncls);
+  const size_t o_tw = off;
+  off += al(sizeof(void*) * ncls);
+  const size_t o_ph = off;
+  off += al(sizeof(void*) * ncls);
+  const size_t o_work = off;
+  off += al(sizeof(Work) * m);
+  const size_t o_st = off;
+  off += al(sizeof(int) * nstatus);
+  std::vector<size_t> o_items(nchunks);
+  for (int k = 0; k < nchunks; ++k) {
+    o_items[k] = off;
+    size_t cnt = ci[k].spread.size() + ci[k].last.size();
+    for (int ip = 0; ip < kMaxPass - 1; ++ip) cnt += ci[k].pass[ip].size();
+    off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 1);
+  }
+  const size_t dev_bytes = off + 256;
+  if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_max > ctx->budget)
+    return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
+  he = hipStreamSynchronize(stream);
+  if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
+  if (B.dev_bytes < dev_bytes) {
+    if (B.dev) (void)hipFree(B.dev);
+    B.dev = nullptr;
+    B.dev_bytes = 0;
+    if (hipMalloc(&B.dev, dev_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch descriptors failed");
+    }
+    B.dev_bytes = dev_bytes;
+  }
+  if (B.ws_bytes < ws_max) {
+    if (B.ws) (void)hipFree(B.ws);
+    B.ws = nullptr;
+    B.ws_bytes = 0;
+    if (hipMalloc(&B.ws, ws_max) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch workspace failed");
+    }
+    B.ws_bytes = ws_max;
+  }
+  if (B.status_cap < (size_t)nstatus) {
+    if (B.status_host) (void)hipHostFree(B.status_host);
+    B.status_host = nullptr;
+    he = hipHostMalloc(reinterpret_cast<void**>(&B.status_host), sizeof(int32_t) * nstatus);
+    if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "pinned status buffer");
+    B.status_cap = nstatus;
+  }
+  // workspaces of each chunk start at the base of the shared buffer
+  std::vector<Work> works(m);
+  for (int k = 0; k < nchunks; ++k) {
+    size_t woff = 0;
+    for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
+      layout_work(plans[cls_of[c]], cur[c].nd, 3, B.ws + woff, &works[c], true);
+      woff += wsz[c];
+    }
+  }
+  he = hipMemcpy(B.dev + o_cur, cur.data(), sizeof(BatchCurve) * m, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(B.dev + o_tw, twp.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(B.dev + o_ph, php.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
+  if (he == hipSuccess)
+    he = hipMemcpy(B.dev + o_work, works.data(), sizeof(Work) * m, hipMemcpyHostToDevice);
+  B.launches.assign(nchunks, BatchLaunch{});
+  for (int k = 0; k < nchunks && he == hipSuccess; ++k) {
+    BatchLaunch& L = B.launches[k];
+    const int64_t c0 = chunk_begin[k];
+    BatchArgs& ba = L.args;
+    ba.curves = reinterpret_cast<const BatchCurve*>(B.dev + o_cur) + c0;
+    ba.ncurves = (int)(chunk_begin[k + 1] - c0);
+    ba.plans = reinterpret_cast<const Plan*>(B.dev + o_plan);
+    ba.tw = reinterpret_cast<const void* const*>(B.dev + o_tw);
+    ba.inv_phihat = reinterpret_cast<const double* const*>(B.dev + o_ph);
+    ba.works = reinterpret_cast<const Work*>(B.dev + o_work) + c0;
+    ba.t = t;
+    ba.y = y;
+    ba.dy = dy;
+    ba.power = power;
+    ba.norm = common->normalization;
+    ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
+    ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
+    ba.status = reinterpret_cast<int*>(B.dev + o_st);
+    L.prec = prec;
+    size_t io = o_items[k];
+    auto put = [&](const std::vector<BatchItem>& v) -> const BatchItem* {
+      const BatchItem* ptr = reinterpret_cast<const BatchItem*>(B.dev + io);
+      if (!v.empty() && he == hipSuccess)
+        he = hipMemcpy(B.dev + io, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice);
+      io += al(sizeof(BatchItem) * v.size()) + 256;
+      return ptr;
+    };
+    L.spread_items = put(ci[k].spread);
+    L.nspread = (int)ci[k].spread.size();
+    for (int ip = 0; ip < kMaxPass - 1; ++ip) {
+      L.pass_items[ip] = put(ci[k].pass[ip]);
+      L.npass_items[ip] = (int)ci[k].pass[ip].size();
+      L.pass_lds[ip] = pass_lds[ip];
+    }
+    L.last_items = put(ci[k].last);
+    L.nlast = (int)ci[k].last.size();
+    L.last_lds = last_lds;
+  }
+  if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
+  B.status_dev = reinterpret_cast<int*>(B.dev + o_st);
+  if (B.exec) (void)hipGraphExecDestroy(B.exec);
+  if (B.graph) (void)hipGraphDestroy(B.graph);
+  B.exec = nullptr;
+  B.graph = nullptr;
+  B.ncurves = nstatus;
+  return MILS_OK;
+}
+
+hipError_t launch_all(const BatchState& B, hipStream_t s) {
+  for (const BatchLaunch& L : B.launches) {
+    hipError_t e = launch_batch(L, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Half-octave band of a series by its number of frequencies (the unit of the
+// batch autotuner).
+int nf_band(int64_t nf) { return (int)std::floor(2.0 * std::log2((double)nf)); }
+
+bool autotune_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("MILS_AUTOTUNE");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// Batch autotuner: for each band of N_f with at least kTuneMin series that
+// has no decision yet for (eps, precision), time a sample of its series
+// (up to kTuneSample, spread over the band) under each candidate (sigma,
+// largest spreading tile) and keep the fastest.  Candidates: the planner's
+// sigma and larger ones (a wider grid with a narrower kernel), tiles of 1024
+// and 256 cells.  The sample runs through the same launches as the batch and
+// writes the sampled series' own outputs (rewritten by the real run).
+constexpr int kTuneMin = 16, kTuneSample = 48;
+int autotune_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, const double* t,
+                   const double* y, const double* dy, const int64_t* nf_off, const double* f0,
+                   const double* df, const mils_params* common, double* power,
+                   hipStream_t stream) {
+  const int prec = common->precision;
+  std::map<int, std::vector<int64_t>> bands;
+  for (int64_t c = 0; c < ncurves; ++c) bands[nf_band(nf_off[c + 1] - nf_off[c])].push_back(c);
+  std::vector<std::pair<double, int>> cand;
+  for (double sg : prec == 1 ? std::vector<double>{0.0, 2.0} : std::vector<double>{0.0, 1.5, 2.0})
+    for (int tm : {1024, 256}) cand.push_back({sg, tm});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) return hip_fail(ctx, he, "autotuner events");
+  int rc = MILS_OK;
+  BatchState T;
+  for (auto& kv : bands) {
+    const auto key = std::make_tuple(kv.first, common->eps, prec);
+    if (ctx->tuned.count(key) || (int)kv.second.size() < kTuneMin) continue;
+    std::vector<int64_t> sample;
+    const int64_t nb = (int64_t)kv.second.size();
+    const int64_t ns = std::min<int64_t>(nb, kTuneSample);
+    for (int64_t i = 0; i < ns; ++i) sample.push_back(kv.second[(size_t)(i * nb / ns)]);
+    double best_ms = 1e300;
+    std::pair<double, int> best = cand[0];
+    for (const auto& cv : cand) {
+      std::vector<double> sig(sample.size(), cv.first);
+      std::vector<int> tm(sample.size(), cv.second);
+      rc = build_batch(ctx, T, sample, sig, tm, nd_off, t, y, dy, nf_off, f0, df, common, power,
+                       ncurves, stream);
+      if (rc == MILS_ERR_UNSUPPORTED) {  // this sigma does not plan for the band
+        rc = MILS_OK;
+        continue;
+      }
+      if (rc != MILS_OK) break;
+      he = launch_all(T, stream);  // warm-up
+      if (he == hipSuccess) he = hipEventRecord(e0, stream);
+      if (he == hipSuccess) he = launch_all(T, stream);
+      if (he == hipSuccess) he = hipEventRecord(e1, stream);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        rc = hip_fail(ctx, he, "autotuner run");
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cv;
+      }
+    }
+    if (rc != MILS_OK) break;
+    ctx->tuned[key] = best;
+  }
+  (void)hipStreamSynchronize(stream);
+  free_batch_state(T);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, const double* t,
                    const double* y, const double* dy, const int64_t* nf_off, const double* f0,
                    const double* df, const mils_params* common, double* power,
@@ -546,6 +902,22 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   BatchState& B = ctx->batch;
   const int prec = common->precision;
+  if (use_graph && autotune_enabled()) {
+    int rc = autotune_batch(ctx, ncurves, nd_off, t, y, dy, nf_off, f0, df, common, power, stream);
+    if (rc != MILS_OK) return rc;
+  }
+  // per-series plan choices: the band's tuned decision, else the planner's
+  std::vector<int64_t> idx(ncurves);
+  std::vector<double> sig(ncurves, 0.0);
+  std::vector<int> tmax(ncurves, 0);
+  for (int64_t c = 0; c < ncurves; ++c) {
+    idx[c] = c;
+    auto it = ctx->tuned.find(std::make_tuple(nf_band(nf_off[c + 1] - nf_off[c]), common->eps, prec));
+    if (it != ctx->tuned.end()) {
+      sig[c] = it->second.first;
+      tmax[c] = it->second.second;
+    }
+  }
 
   uint64_t key = 1469598103934665603ull;
   key = fnv1a(key, &ncurves, sizeof(ncurves));
@@ -556,254 +928,19 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
   key = fnv1a(key, &common->eps, sizeof(double));
   key = fnv1a(key, &common->precision, sizeof(int32_t) * 2);
   key = fnv1a(key, &common->flags, sizeof(uint32_t));
+  key = fnv1a(key, sig.data(), sizeof(double) * ncurves);
+  key = fnv1a(key, tmax.data(), sizeof(int) * ncurves);
   const void* ptrs[4] = {t, y, dy, power};
   key = fnv1a(key, ptrs, sizeof(ptrs));
 
   if (!(B.valid && B.key == key)) {
     B.valid = false;
-    // grid size of each series, then grid-size classes (ratio <= 1.06) that share a plan
-    std::vector<int64_t> ngrid(ncurves);
-    for (int64_t c = 0; c < ncurves; ++c) {
-      const int64_t nf = nf_off[c + 1] - nf_off[c];
-      auto k = std::make_tuple(nf, prec, common->eps);
-      auto it = B.grid_of_nf.find(k);
-      if (it == B.grid_of_nf.end()) {
-        Plan pl;
-        std::string err;
-        PlanRequest r{nf, common->eps, prec, 3};
-        r.batch = true;
-        if (!make_plan(r, &pl, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
-        it = B.grid_of_nf.emplace(k, pl.n).first;
-      }
-      ngrid[c] = it->second;
-    }
-    std::vector<int64_t> ns(ngrid);
-    std::sort(ns.begin(), ns.end());
-    ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
-    std::map<int64_t, int> cls_of_n;
-    std::vector<int64_t> cls_n;
-    for (size_t i = 0; i < ns.size();) {
-      size_t j = i;
-      while (j + 1 < ns.size() && (double)ns[j + 1] <= 1.06 * (double)ns[i]) ++j;
-      const int cid = (int)cls_n.size();
-      cls_n.push_back(ns[j]);
-      for (size_t q = i; q <= j; ++q) cls_of_n[ns[q]] = cid;
-      i = j + 1;
-    }
-    const int ncls = (int)cls_n.size();
-    std::vector<int64_t> cls_nf(ncls, 1);
-    std::vector<int> cls_of(ncurves);
-    for (int64_t c = 0; c < ncurves; ++c) {
-      cls_of[c] = cls_of_n[ngrid[c]];
-      cls_nf[cls_of[c]] = std::max<int64_t>(cls_nf[cls_of[c]], nf_off[c + 1] - nf_off[c]);
-    }
-    std::vector<Plan> plans(ncls);
-    std::vector<const void*> twp(ncls);
-    std::vector<const double*> php(ncls);
-    for (int k = 0; k < ncls; ++k) {
-      PlanEntry* pe = nullptr;
-      int rc = get_plan(ctx, cls_nf[k], common->eps, prec, 3, &pe, true, true, cls_n[k]);
-      if (rc != MILS_OK) return rc;
-      plans[k] = pe->plan;
-      twp[k] = pe->tw;
-      php[k] = pe->inv_phihat;
-    }
-    // series descriptors and their workspaces; chunks whose workspaces fit the cap
-    std::vector<BatchCurve> cur(ncurves);
-    std::vector<size_t> wsz(ncurves);
-    for (int64_t c = 0; c < ncurves; ++c) {
-      BatchCurve& d = cur[c];
-      d.t_off = nd_off[c];
-      d.nd = nd_off[c + 1] - nd_off[c];
-      d.out_off = nf_off[c];
-      d.nf = nf_off[c + 1] - nf_off[c];
-      d.K = d.nf / 2;
-      d.f0 = f0[c];
-      d.df = df[c];
-      centre_frequency(d.f0, d.df, d.K, &d.fch, &d.fcl);
-      d.kzero = zero_index(d.f0, d.df, d.nf);
-      d.plan = cls_of[c];
-      d.index = (int)c;
-      wsz[c] = (layout_work(plans[cls_of[c]], d.nd, 3, nullptr, nullptr, true) + 255) & ~(size_t)255;
-    }
-    size_t cap = kBatchWorkspaceCap;
-    if (ctx->budget) {
-      const size_t used = ctx->plan_bytes + ctx->ws_bytes;
-      cap = ctx->budget > used ? std::min<size_t>(cap, (ctx->budget - used) / 2) : 0;
-    }
-    std::vector<int64_t> chunk_begin{0};
-    size_t acc = 0, ws_max = 0;
-    for (int64_t c = 0; c < ncurves; ++c) {
-      if (wsz[c] > cap) return fail(ctx, MILS_ERR_OOM, "a series of the batch exceeds the HBM budget");
-      if (acc + wsz[c] > cap) {
-        chunk_begin.push_back(c);
-        ws_max = std::max(ws_max, acc);
-        acc = 0;
-      }
-      acc += wsz[c];
-    }
-    ws_max = std::max(ws_max, acc);
-    chunk_begin.push_back(ncurves);
-    const int nchunks = (int)chunk_begin.size() - 1;
-    // work items of every chunk
-    struct ChunkItems {
-      std::vector<BatchItem> spread, pass[kMaxPass - 1], last;
-    };
-    std::vector<ChunkItems> ci(nchunks);
-    for (int k = 0; k < nchunks; ++k) {
-      for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
-        const Plan& q = plans[cls_of[c]];
-        const int lc = (int)(c - chunk_begin[k]);
-        for (int64_t tl = 0; tl < q.n / q.T; ++tl) ci[k].spread.push_back({lc, (int)tl});
-        for (int ip = 0; ip + 1 < q.npass; ++ip) {
-          const FftPass& ps = q.pass[ip];
-          const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-          for (int64_t x = 0; x < 3 * nblk; ++x) ci[k].pass[ip].push_back({lc, (int)x});
-        }
-        const FftPass& ls = q.pass[q.npass - 1];
-        for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x});
-      }
-    }
-    // dynamic LDS of each pass launch (largest class that takes part)
-    size_t pass_lds[kMaxPass - 1] = {0, 0, 0}, last_lds = 0;
-    const size_t elem = prec == 1 ? 8 : 16;
-    for (int k = 0; k < ncls; ++k) {
-      const Plan& q = plans[k];
-      for (int ip = 0; ip + 1 < q.npass; ++ip) {
-        const FftPass& ps = q.pass[ip];
-        pass_lds[ip] = std::max(pass_lds[ip], elem * (size_t)(ps.L * ps.C + ps.L) + ps.L + 16);
-      }
-      const FftPass& ls = q.pass[q.npass - 1];
-      last_lds = std::max(last_lds, elem * (size_t)(ls.L * last_pitch(3 * ls.C) + ls.L));
-    }
-    // device layout: curves, plans, table pointers, works, items, status
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t off = 0;
-    const size_t o_cur = off;
-    off += al(sizeof(BatchCurve) * ncurves);
-    const size_t o_plan = off;
-    off += al(sizeof(Plan) * ncls);
-    const size_t o_tw = off;
-    off += al(sizeof(void*) * ncls);
-    const size_t o_ph = off;
-    off += al(sizeof(void*) * ncls);
-    const size_t o_work = off;
-    off += al(sizeof(Work) * ncurves);
-    const size_t o_st = off;
-    off += al(sizeof(int) * ncurves);
-    std::vector<size_t> o_items(nchunks);
-    for (int k = 0; k < nchunks; ++k) {
-      o_items[k] = off;
-      size_t cnt = ci[k].spread.size() + ci[k].last.size();
-      for (int ip = 0; ip < kMaxPass - 1; ++ip) cnt += ci[k].pass[ip].size();
-      off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 1);
-    }
-    const size_t dev_bytes = off + 256;
-    if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_max > ctx->budget)
-      return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
-    he = hipStreamSynchronize(stream);
-    if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
-    if (B.dev_bytes < dev_bytes) {
-      if (B.dev) (void)hipFree(B.dev);
-      B.dev = nullptr;
-      B.dev_bytes = 0;
-      if (hipMalloc(&B.dev, dev_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch descriptors failed");
-      }
-      B.dev_bytes = dev_bytes;
-    }
-    if (B.ws_bytes < ws_max) {
-      if (B.ws) (void)hipFree(B.ws);
-      B.ws = nullptr;
-      B.ws_bytes = 0;
-      if (hipMalloc(&B.ws, ws_max) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch workspace failed");
-      }
-      B.ws_bytes = ws_max;
-    }
-    if (B.status_cap < (size_t)ncurves) {
-      if (B.status_host) (void)hipHostFree(B.status_host);
-      B.status_host = nullptr;
-      he = hipHostMalloc(reinterpret_cast<void**>(&B.status_host), sizeof(int32_t) * ncurves);
-      if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "pinned status buffer");
-      B.status_cap = ncurves;
-    }
-    // workspaces of each chunk start at the base of the shared buffer
-    std::vector<Work> works(ncurves);
-    for (int k = 0; k < nchunks; ++k) {
-      size_t woff = 0;
-      for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
-        layout_work(plans[cls_of[c]], cur[c].nd, 3, B.ws + woff, &works[c], true);
-        woff += wsz[c];
-      }
-    }
-    he = hipMemcpy(B.dev + o_cur, cur.data(), sizeof(BatchCurve) * ncurves, hipMemcpyHostToDevice);
-    if (he == hipSuccess)
-      he = hipMemcpy(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls, hipMemcpyHostToDevice);
-    if (he == hipSuccess)
-      he = hipMemcpy(B.dev + o_tw, twp.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
-    if (he == hipSuccess)
-      he = hipMemcpy(B.dev + o_ph, php.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
-    if (he == hipSuccess)
-      he = hipMemcpy(B.dev + o_work, works.data(), sizeof(Work) * ncurves, hipMemcpyHostToDevice);
-    B.launches.assign(nchunks, BatchLaunch{});
-    for (int k = 0; k < nchunks && he == hipSuccess; ++k) {
-      BatchLaunch& L = B.launches[k];
-      const int64_t c0 = chunk_begin[k];
-      BatchArgs& ba = L.args;
-      ba.curves = reinterpret_cast<const BatchCurve*>(B.dev + o_cur) + c0;
-      ba.ncurves = (int)(chunk_begin[k + 1] - c0);
-      ba.plans = reinterpret_cast<const Plan*>(B.dev + o_plan);
-      ba.tw = reinterpret_cast<const void* const*>(B.dev + o_tw);
-      ba.inv_phihat = reinterpret_cast<const double* const*>(B.dev + o_ph);
-      ba.works = reinterpret_cast<const Work*>(B.dev + o_work) + c0;
-      ba.t = t;
-      ba.y = y;
-      ba.dy = dy;
-      ba.power = power;
-      ba.norm = common->normalization;
-      ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
-      ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
-      ba.status = reinterpret_cast<int*>(B.dev + o_st);
-      L.prec = prec;
-      size_t io = o_items[k];
-      auto put = [&](const std::vector<BatchItem>& v) -> const BatchItem* {
-        const BatchItem* ptr = reinterpret_cast<const BatchItem*>(B.dev + io);
-        if (!v.empty() && he == hipSuccess)
-          he = hipMemcpy(B.dev + io, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice);
-        io += al(sizeof(BatchItem) * v.size()) + 256;
-        return ptr;
-      };
-      L.spread_items = put(ci[k].spread);
-      L.nspread = (int)ci[k].spread.size();
-      for (int ip = 0; ip < kMaxPass - 1; ++ip) {
-        L.pass_items[ip] = put(ci[k].pass[ip]);
-        L.npass_items[ip] = (int)ci[k].pass[ip].size();
-        L.pass_lds[ip] = pass_lds[ip];
-      }
-      L.last_items = put(ci[k].last);
-      L.nlast = (int)ci[k].last.size();
-      L.last_lds = last_lds;
-    }
-    if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
-    B.status_dev = reinterpret_cast<int*>(B.dev + o_st);
-    if (B.exec) (void)hipGraphExecDestroy(B.exec);
-    if (B.graph) (void)hipGraphDestroy(B.graph);
-    B.exec = nullptr;
-    B.graph = nullptr;
-    B.ncurves = ncurves;
+    int rc = build_batch(ctx, B, idx, sig, tmax, nd_off, t, y, dy, nf_off, f0, df, common, power,
+                         ncurves, stream);
+    if (rc != MILS_OK) return rc;
     B.key = key;
     B.valid = true;
   }
-  auto launch_all = [&](hipStream_t s) -> hipError_t {
-    for (const BatchLaunch& L : B.launches) {
-      hipError_t e = launch_batch(L, s);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
   if (use_graph && !B.exec) {
     // capture the launches once per batch layout
     if (!B.cap_stream) {
@@ -812,14 +949,14 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
     }
     he = hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
-      hipError_t le = launch_all(B.cap_stream);
+      hipError_t le = launch_all(B, B.cap_stream);
       he = hipStreamEndCapture(B.cap_stream, &B.graph);
       if (le != hipSuccess) he = le;
     }
     if (he == hipSuccess) he = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
     if (he != hipSuccess) return hip_fail(ctx, he, "batch graph capture");
   }
-  he = use_graph ? hipGraphLaunch(B.exec, stream) : launch_all(stream);
+  he = use_graph ? hipGraphLaunch(B.exec, stream) : launch_all(B, stream);
   if (he == hipSuccess)
     he = hipMemcpyAsync(B.status_host, B.status_dev, sizeof(int32_t) * ncurves,
                         hipMemcpyDeviceToHost, stream);
@@ -845,6 +982,16 @@ int mils_periodogram_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd
                            void* hip_stream) {
   return mils_batch_run(ctx, ncurves, nd_off, t, y, dy, nf_off, f0, df, common, power,
                         status_per_curve, hip_stream, true);
+}
+
+int mils_batch_tuning(mils_context* ctx, int64_t nf, double eps, int32_t precision, double* sigma,
+                      int32_t* tile_max) {
+  if (!ctx || !sigma || !tile_max || nf < 1) return MILS_ERR_INVALID_ARG;
+  auto it = ctx->tuned.find(std::make_tuple(nf_band(nf), eps, (int)precision));
+  if (it == ctx->tuned.end()) return MILS_ERR_INVALID_ARG;
+  *sigma = it->second.first;
+  *tile_max = it->second.second;
+  return MILS_OK;
 }
 
 int mils_profile_enable(mils_context* ctx, int enable) {

@@ -372,7 +372,8 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     }
   }
   int T = 1;
-  for (int d = (int)std::min<int64_t>(p.S1, kTileMaxCells); d >= 1; --d)
+  const int tmax = r.tile_max > 0 ? std::min(r.tile_max, kTileMaxCells) : kTileMaxCells;
+  for (int d = (int)std::min<int64_t>(p.S1, tmax); d >= 1; --d)
     if (p.S1 % d == 0) {
       T = d;
       break;

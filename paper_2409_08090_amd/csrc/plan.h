@@ -20,6 +20,7 @@ struct PlanRequest {
   double sigma = 0.0;   // upsampling factor; 0 = the precision's default
   bool batch = false;   // plan for the batched kernels (no big passes)
   int64_t n_fixed = 0;  // use exactly this grid size (must factor), 0 = choose
+  int tile_max = 0;     // largest spreading tile (cells), 0 = kTileMax
 };
 
 // Default upsampling factor of a precision.

@@ -93,6 +93,9 @@ SIGNATURES = {
     "mils_context_destroy": ([_P], ctypes.c_int),
     "mils_plan_info": ([_P, ctypes.c_int64, ctypes.POINTER(mils_params),
                         ctypes.POINTER(mils_plan_desc)], ctypes.c_int),
+    "mils_batch_tuning": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
+                          ctypes.c_int),
     "mils_kernel_table": ([_P, ctypes.POINTER(mils_params), _P, ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -190,6 +193,15 @@ class Context:
         lib = load()
         return {lib.mils_profile_stage_name(i).decode(): (float(ms[i]), int(n[i]))
                 for i in range(MILS_NUM_STAGES) if n[i]}
+
+    def batch_tuning(self, nf: int, eps: float, precision: str = "fp64"):
+        """(sigma, tile_max) the batch autotuner chose for series of nf
+        frequencies (sigma 0.0: the planner's choice), or None if undecided."""
+        sg = ctypes.c_double()
+        tm = ctypes.c_int32()
+        rc = load().mils_batch_tuning(self.handle, int(nf), float(eps), PRECISIONS[precision],
+                                      ctypes.byref(sg), ctypes.byref(tm))
+        return (sg.value, tm.value) if rc == MILS_OK else None
 
     def check(self, rc: int):
         if rc != MILS_OK:

@@ -226,3 +226,13 @@ def test_kernel_polynomials_reproduce_the_es_kernel(nf, eps, prec):
     assert worst <= bound, (w, beta, worst, bound)
     # and well below the tolerance the plan was made for
     assert worst <= eps / 10
+
+
+def test_batch_tuning_query_without_a_decision():
+    ctx = mils.Context(-1)
+    assert ctx.batch_tuning(12_000, 1e-9, "fp64") is None
+    lib = mils.load()
+    import ctypes as C
+    sg, tm = C.c_double(), C.c_int32()
+    assert lib.mils_batch_tuning(ctx.handle, 0, 1e-9, 0, C.byref(sg), C.byref(tm)) == mils.MILS_ERR_INVALID_ARG
+    ctx.close()

@@ -114,3 +114,31 @@ def test_full_batch_workload_sampled(precision):
           flush=True)
     assert worst <= TOL[precision]
     assert all(np.all(np.isfinite(p)) for p in powers)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotuner_decides_per_band_and_keeps_parity(precision):
+    # 40 series in one half-octave band of N_f: the first batch on a fresh
+    # context times the candidate (sigma, tile) pairs on a sample of them
+    rng = np.random.default_rng(21)
+    curves = [workloads.batch_curve(rng, int(n)) for n in rng.integers(1500, 1700, 40)]
+    ctx = mils.Context(0)
+    try:
+        t, y, dy, nd_off, nf_off, f0, df = mils.pack_curves(curves)
+        out, st = mils.periodogram_batch(t, y, dy, nd_off, nf_off, f0, df, eps=EPS[precision],
+                                         precision=precision, ctx=ctx, return_status=True)
+        torch.cuda.synchronize()
+        assert np.all(st == 0)
+        dec = ctx.batch_tuning(curves[0].nf, EPS[precision], precision)
+        sigmas = (0.0, 1.5, 2.0) if precision == "fp64" else (0.0, 2.0)
+        assert dec is not None and dec[0] in sigmas and dec[1] in (1024, 256), dec
+        powers = mils.split_power(out, nf_off)
+        worst = 0.0
+        for c, p in zip(curves[::8], powers[::8]):
+            k = sample_k(c.nf, rng, 200)
+            ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+            worst = max(worst, np.max(np.abs(p[k] - ref)) / np.max(np.abs(ref)))
+        print(f"[autotuned {precision}] decision {dec}, worst error {worst:.3e}", flush=True)
+        assert worst <= TOL[precision]
+    finally:
+        ctx.close()
