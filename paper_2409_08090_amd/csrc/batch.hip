@@ -260,6 +260,7 @@ template <typename Real, int GEO, int NG>
 __global__ __launch_bounds__(NT) void k_bspread(BatchArgs ba, const BatchItem* items) {
   __shared__ Real acc[NG * 2 * kTileMax];
   __shared__ int rb[8], re[8], sv[2];
+  __shared__ SpreadRecords<Real, NG, NT> rec;
   __shared__ Plan sp;
   const BatchItem it = items[blockIdx.x];
   const BatchCurve c = ba.curves[it.curve];
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_bspread(BatchArgs ba, const BatchItem* i
   __syncthreads();
   const CallArgs a = curve_args(ba, c);
   spread_tile<Real, GEO, NG, NT, true>(it.sub, sp.T, kTileMax, a, sp, w, st, GEO == 1 ? 0 : 2,
-                                       nullptr, acc, rb, re, sv);
+                                       nullptr, acc, rb, re, sv, rec);
 }
 
 // A first/middle FFT pass ip: one workgroup per (series, grid, column block).

@@ -327,6 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Wo
                                                           const int* act_rows, int slot) {
   __shared__ Real acc[NG * 2 * kTileMax];
   __shared__ int rb[8], re[8], sv[2];
+  __shared__ SpreadRecords<Real, NG, kThreads> rec;
   const DevStats* stp = w.stats;
   if (stp->status != 0) return;
   const int tpr = (int)(p.S1 / p.T);
@@ -335,7 +336,7 @@ __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Wo
     const int q = t / tpr;
     const int tile = act_rows[q] * tpr + (t - q * tpr);
     spread_tile<Real, GEO, NG, kThreads, true>(tile, p.T, kTileMax, a, p, w, *stp, gbase, nullptr,
-                                               acc, rb, re, sv);
+                                               acc, rb, re, sv, rec);
   }
 }
 

@@ -94,36 +94,6 @@ __device__ __forceinline__ int gather_ranges(int* rb, int* re, int64_t c0, int64
 template <typename Real>
 using ConstPtr = const __attribute__((address_space(4))) Real*;
 
-// The w kernel values of a point (plan table hc, see kHornerK): each
-// polynomial as a sum of coefficient x power of u, the powers formed once per
-// point, so that every term is one multiply-add with the coefficient taken
-// straight from a scalar register (|u| <= 1 and the coefficients are below
-// one in magnitude: as accurate as Horner's rule).  Groups of four cells past
-// the width are skipped.
-template <typename Real>
-__device__ __forceinline__ void horner_kernel(ConstPtr<Real> hc, Real u, int wd, Real* ker) {
-  constexpr int NC = sizeof(Real) == 8 ? kHornerN64 : kHornerN32;
-  Real pw[NC];
-  pw[0] = (Real)1;
-  pw[1] = u;
-#pragma unroll
-  for (int i = 2; i < NC; ++i) pw[i] = pw[i / 2] * pw[i - i / 2];
-#pragma unroll
-  for (int k0 = 0; k0 < kHornerK; k0 += 4) {
-    if (k0 < wd) {
-#pragma unroll
-      for (int k = k0; k < k0 + 4; ++k) ker[k] = hc[(NC - 1) * kHornerK + k];
-#pragma unroll
-      for (int i = 1; i < NC; ++i)
-#pragma unroll
-        for (int k = k0; k < k0 + 4; ++k) ker[k] += hc[(NC - 1 - i) * kHornerK + k] * pw[i];
-    } else {
-#pragma unroll
-      for (int k = k0; k < k0 + 4; ++k) ker[k] = 0;
-    }
-  }
-}
-
 // Whether any kernel support of geometry GEO reaches row r of the
 // [nrows][S1] view of the grid (h: half-width in cells, rounded up, plus one).
 template <int GEO>
@@ -134,6 +104,18 @@ __device__ __forceinline__ bool row_active(int64_t r, int h, const Plan& p, cons
   for (int i = 0; i < cnt; ++i) tot += re[i] - rb[i];
   return tot > 0;
 }
+
+// Per-point records of one chunk of NT points of a spreading tile (LDS): the
+// first covered cell relative to the tile (kSpreadNone: the point misses the
+// tile), the kernel argument u and the NG complex strengths (component c of
+// grid g at h[(2g + c) NT + i]).
+constexpr int kSpreadNone = -(1 << 30);
+template <typename Real, int NG, int NT>
+struct SpreadRecords {
+  int lb[NT];
+  Real u[NT];
+  Real h[2 * NG * NT];
+};
 
 // Spread one tile of geometry GEO into NG grids: cells [tile*T, tile*T + T)
 // of the flat grid, where T either divides the row length S1 of the
@@ -146,7 +128,8 @@ __device__ __forceinline__ bool row_active(int64_t r, int h, const Plan& p, cons
 template <typename Real, int GEO, int NG, int NT, bool KNOWN = false>
 __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const Plan& p,
                             const Work& w, const DevStats& st, int gbase, unsigned char* rowflag,
-                            Real* acc, int* rb, int* re, int* sv) {
+                            Real* acc, int* rb, int* re, int* sv,
+                            SpreadRecords<Real, NG, NT>& rec) {
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
   const int64_t a0 = (int64_t)tile * Tt;
@@ -198,7 +181,6 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
   const double nreal = (double)p.n;
   const int wd = p.w;
   const double hw = p.hw;
-  const ConstPtr<Real> hc = (ConstPtr<Real>)(p.hcoef);
   // a kernel support can meet the tile at most once unless the tile spans
   // nearly the whole periodic grid
   const bool wrap_free = T <= n - wd;
@@ -206,66 +188,104 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
   const double* yy = a.periodogram ? (sorted ? a.y : w.ys) : (sorted ? a.h : w.hs);
   const double* dd = sorted ? a.dy : w.dys;
   const bool have_dy = a.periodogram && (sorted ? a.dy != nullptr : true);
+  // Lane layout of the accumulation: KL consecutive lanes take one point,
+  // lane kk adding the kernel value at the point's cell lb + kk; each lane
+  // holds the polynomial of its offset kk in registers.  The Q = 64/KL points
+  // a wave takes at once lie a quarter chunk apart in the (sorted) point
+  // order, so their runs of cells do not meet.
+  constexpr int NC = sizeof(Real) == 8 ? kHornerN64 : kHornerN32;
+  const int KL = wd <= 16 ? 16 : 32;
+  const int kk = tid & (KL - 1);
+  const int grp = tid / KL;          // group of KL lanes
+  const int Q = 64 / KL;             // groups per wave
+  const int wave = tid >> 6;
+  const int q = grp - wave * Q;      // group within the wave
+  const int nwave = NT / 64;
+  const ConstPtr<Real> hc = (ConstPtr<Real>)(p.hcoef);
+  Real cf[NC];
+#pragma unroll
+  for (int j = 0; j < NC; ++j) cf[j] = kk < kHornerK ? hc[j * kHornerK + kk] : (Real)0;
   for (int r = 0; r < nr; ++r) {
     const int jend = re[r];
-    for (int j = rb[r] + tid; j < jend; j += NT) {
-      const double t = tt[j];
-      int cell;
-      double frac;
-      grid_coord32(t, tau, gstep, nreal, n, cell, frac);
-      const int o0 = (int)ceil(frac - hw);
-      int lb = cell + o0 - (int)a0;  // in (-2n, n)
-      if (lb < 0) lb += n;
-      if (lb < 0) lb += n;
-      if (lb > n - wd) lb -= n;
-      if (wrap_free && (lb >= T || lb + wd <= 0)) continue;
-      double pc, ps;
-      prephase(t, tau, a.fch, a.fcl, pc, ps);
-      Real hre[NG], him[NG];
-      if (a.periodogram) {
-        double wj = 1.0;
-        if (have_dy) {
-          const double dv = dd[j];
-          wj = 1.0 / (dv * dv);
-        }
-        const double wh = wj * invW;
-        if (GEO == 1) {
-          const double yt = yy[j] - ysub;
-          hre[0] = (Real)(wh * yt * pc);
-          him[0] = (Real)(wh * yt * ps);
-          if (NG > 1) {
-            hre[NG - 1] = (Real)(wh * pc);
-            him[NG - 1] = (Real)(wh * ps);
-          }
-        } else {
-          // exp(2 i theta) from exp(i theta)
-          hre[0] = (Real)(wh * (pc * pc - ps * ps));
-          him[0] = (Real)(wh * (2.0 * pc * ps));
-        }
-      } else {
-        const double hv = yy[j];
-        hre[0] = (Real)(hv * pc);
-        him[0] = (Real)(hv * ps);
-      }
-      // kernel values at cells cell + o0 + k: polynomials in u = 2t - 1 with
-      // t = o0 + hw - frac in [0, 1)
-      Real ker[kHornerK];
-      horner_kernel<Real>(hc, (Real)(2.0 * ((double)o0 + hw - frac) - 1.0), wd, ker);
-#pragma unroll
-      for (int k = 0; k < kHornerK; ++k) {
-        if (k < wd) {
-          int loc = lb + k;
-          if (loc < 0) loc += n;
-          else if (loc >= n) loc -= n;
-          if (loc < T) {
+    for (int base = rb[r]; base < jend; base += NT) {
+      // (1) one point per thread: its record
+      {
+        const int j = base + tid;
+        int lbv = kSpreadNone;
+        if (j < jend) {
+          const double t = tt[j];
+          int cell;
+          double frac;
+          grid_coord32(t, tau, gstep, nreal, n, cell, frac);
+          const int o0 = (int)ceil(frac - hw);
+          int lb = cell + o0 - (int)a0;  // in (-2n, n)
+          if (lb < 0) lb += n;
+          if (lb < 0) lb += n;
+          if (lb > n - wd) lb -= n;
+          if (!(wrap_free && (lb >= T || lb + wd <= 0))) {
+            lbv = lb;
+            double pc, ps;
+            prephase(t, tau, a.fch, a.fcl, pc, ps);
+            Real hre[NG], him[NG];
+            if (a.periodogram) {
+              double wj = 1.0;
+              if (have_dy) {
+                const double dv = dd[j];
+                wj = 1.0 / (dv * dv);
+              }
+              const double wh = wj * invW;
+              if (GEO == 1) {
+                const double yt = yy[j] - ysub;
+                hre[0] = (Real)(wh * yt * pc);
+                him[0] = (Real)(wh * yt * ps);
+                if (NG > 1) {
+                  hre[NG - 1] = (Real)(wh * pc);
+                  him[NG - 1] = (Real)(wh * ps);
+                }
+              } else {
+                // exp(2 i theta) from exp(i theta)
+                hre[0] = (Real)(wh * (pc * pc - ps * ps));
+                him[0] = (Real)(wh * (2.0 * pc * ps));
+              }
+            } else {
+              const double hv = yy[j];
+              hre[0] = (Real)(hv * pc);
+              him[0] = (Real)(hv * ps);
+            }
+            // kernel argument: u = 2t - 1, t = o0 + hw - frac in [0, 1)
+            rec.u[tid] = (Real)(2.0 * ((double)o0 + hw - frac) - 1.0);
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-              atomicAdd(&acc[(2 * g) * tcap + loc], ker[k] * hre[g]);
-              atomicAdd(&acc[(2 * g + 1) * tcap + loc], ker[k] * him[g]);
+              rec.h[(2 * g) * NT + tid] = hre[g];
+              rec.h[(2 * g + 1) * NT + tid] = him[g];
             }
           }
         }
+        rec.lb[tid] = lbv;
       }
+      __syncthreads();
+      // (2) the chunk's points, KL lanes each
+      const int cnt = jend - base < NT ? jend - base : NT;
+      for (int it = 0; it * Q * nwave < NT; ++it) {
+        const int i = q * (NT / Q) + wave + nwave * it;  // point slot
+        if (i >= cnt) continue;
+        const int lb = rec.lb[i];
+        if (lb == kSpreadNone || kk >= wd) continue;
+        int loc = lb + kk;
+        if (loc < 0) loc += n;
+        else if (loc >= n) loc -= n;
+        if (loc >= T) continue;
+        const Real u = rec.u[i];
+        Real v = cf[0];
+#pragma unroll
+        for (int jc = 1; jc < NC; ++jc) v = v * u + cf[jc];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          atomicAdd(&acc[(2 * g) * tcap + loc], v * rec.h[(2 * g) * NT + i]);
+          atomicAdd(&acc[(2 * g + 1) * tcap + loc], v * rec.h[(2 * g + 1) * NT + i]);
+        }
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
