@@ -73,6 +73,7 @@ def byte_model(c, plan, csize):
     ng = 3
     m = {
         "stats": 24.0 * nd,
+        "lowfreq": 24.0 * nd,
         "bin_sort": 8.0 * nd + 4.0 * (n // plan["bin"] + 1),
         "spread_f": 24.0 * nd + 2 * rf * n * csize,
         "spread_2f": 16.0 * nd + r2 * n * csize,
@@ -130,11 +131,17 @@ def main():
     bytes_model, rf, r2 = byte_model(c, plan, 16)
     stages = {}
     for name, (ms, n) in prof.items():
-        avg = ms / n
+        per_step = ms / args.steps
         b = bytes_model.get(name, 0.0)
-        stages[name] = {"avg_ms": round(avg, 5), "alg_bytes": b,
-                        "alg_GBs": round(b / (avg * 1e-3) / 1e9, 1)}
-    dom = max(prof, key=lambda k: prof[k][0])
+        stages[name] = {"ms_per_step": round(per_step, 5),
+                        "launches_per_step": round(n / args.steps, 3), "alg_bytes": b,
+                        "alg_GBs": round(b / (per_step * 1e-3) / 1e9, 1)}
+    # The roofline's kernel: the costliest stage that is one kernel launch per
+    # periodogram (a middle FFT pass or the last pass), so that its average
+    # launch duration is what the kernel trace reports for it.
+    single = [k for k in prof if prof[k][1] == args.steps and
+              (k.startswith("fft_pass_") and k != "fft_pass_0" or k == "fft_last_power")]
+    dom = max(single, key=lambda k: prof[k][0])
     dom_ms = prof[dom][0] / prof[dom][1]
     achieved = bytes_model[dom] / (dom_ms * 1e-3) / 1e9
     traffic = None

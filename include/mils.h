@@ -282,15 +282,19 @@ int mils_server_destroy(mils_server *srv);
 /*
  * Per-stage timing of the single-series path (measurement support).  While
  * enabled, every call records a pair of HIP events around each stage of the
- * path on the call's stream.  Stages: 0 statistics, 1 binning / sort,
+ * path on the stream that runs it.  Stages: 0 statistics, 1 binning / sort,
  * 2 spread (geometry f), 3 spread (geometry 2f), 4-6 FFT passes through HBM
  * (first pass pruned), 7 last FFT pass fused with deconvolution, crop and
- * power.  mils_profile_enable(ctx, 1) clears the accumulators.
+ * power, 8 direct sums near f = 0.  A periodogram runs stages 3, 8 and the
+ * first pass of the 2f grid on a second stream of the context, beside the f
+ * geometry (stage 4 then counts two launches per call, and stages that
+ * overlap share the GPU).  mils_profile_enable(ctx, 1) clears the
+ * accumulators.
  * mils_profile_read waits for the recorded events and adds, per stage, the
  * total elapsed milliseconds and the number of timed launches to ms_total[s]
  * and launches[s] (host arrays of MILS_NUM_STAGES entries), then clears them.
  */
-enum { MILS_NUM_STAGES = 8 };
+enum { MILS_NUM_STAGES = 9 };
 int mils_profile_enable(mils_context *ctx, int enable);
 const char *mils_profile_stage_name(int stage);
 int mils_profile_read(mils_context *ctx, double *ms_total, int64_t *launches);

@@ -131,6 +131,9 @@ struct mils_context {
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_recs;
   std::vector<hipEvent_t> prof_pool;
   int num_cu = 256;
+  // second stream (default priority) and fork/join events of a periodogram
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   BatchState batch;
   // batch autotuner: (N_f band, eps, precision) -> (sigma, largest spreading tile)
   std::map<std::tuple<int, double, int>, std::pair<double, int>> tuned;
@@ -335,7 +338,8 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.power = power;
   a.sums = sums;
   StageHook hook{prof_hook, ctx};
-  he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr);
+  AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
+  he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr, ctx->aux ? &aux : nullptr);
   if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
   ctx->last_stats = w.stats;
   ctx->last_stream = stream;
@@ -394,6 +398,9 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
     if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), 64);
     if (he == hipSuccess)
       he = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (he != hipSuccess) {
       std::lock_guard<std::mutex> lk(g_err_mu);
       g_create_err = std::string("context init: ") + hipGetErrorString(he);
@@ -414,6 +421,9 @@ int mils_context_destroy(mils_context* ctx) {
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
     free_batch_state(ctx->batch);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->host_status) (void)hipHostFree(ctx->host_status);
     for (auto& r : ctx->prof_recs) {
       (void)hipEventDestroy(std::get<1>(r));
@@ -1006,8 +1016,9 @@ int mils_profile_enable(mils_context* ctx, int enable) {
 }
 
 const char* mils_profile_stage_name(int stage) {
-  static const char* names[kNumStages] = {"stats",      "bin_sort",   "spread_f",   "spread_2f",
-                                          "fft_pass_0", "fft_pass_1", "fft_pass_2", "fft_last_power"};
+  static const char* names[kNumStages] = {"stats",      "bin_sort",   "spread_f",
+                                          "spread_2f",  "fft_pass_0", "fft_pass_1",
+                                          "fft_pass_2", "fft_last_power", "lowfreq"};
   if (stage < 0 || stage >= kNumStages) return "";
   return names[stage];
 }

@@ -15,7 +15,15 @@ enum Stage {
   kStageSpread2F = 3,
   kStagePass0 = 4,  // first FFT pass (pruned), then 5, 6 for later middle passes
   kStageLast = 7,   // last FFT pass + deconvolution + power
-  kNumStages = 8
+  kStageLow = 8,    // direct sums near f = 0
+  kNumStages = 9
+};
+
+// A second stream for the 2f geometry of a periodogram, with the events
+// that fork it from and join it back to the call's stream.
+struct AuxStream {
+  hipStream_t s;
+  hipEvent_t fork, join;
 };
 
 // Optional hook called before (begin = 1) and after (begin = 0) each stage is
@@ -28,7 +36,7 @@ struct StageHook {
 // Enqueue the whole single-series path (statistics, binning, spread, FFT
 // passes, deconvolution and power or raw sums) on stream s.
 hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
-                       const StageHook* hook = nullptr);
+                       const StageHook* hook = nullptr, const AuxStream* aux = nullptr);
 
 // 1 / phihat(m) for m = 0..K by Gauss-Legendre quadrature of the kernel.
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,

@@ -491,27 +491,26 @@ hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, cons
 
 template <typename Real>
 static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
-                                const StageHook* hook) {
+                                const StageHook* hook, const AuxStream* aux) {
   using T2 = typename cplx<Real>::T;
   constexpr bool f64 = sizeof(Real) == 8;
   constexpr int EMID = f64 ? kEmid64 : kEmid32;
   constexpr int ELAST = f64 ? kElast64 : kElast32;
   constexpr int EBIG = f64 ? kEbig64 : kEbig32;
   const int G = a.periodogram ? 3 : 1;
-  auto mark = [&](int stage, int begin) {
-    if (hook) hook->fn(hook->ud, stage, begin, s);
+  // The periodogram forks after binning: the 2f geometry (row flags, spread,
+  // first FFT pass of its grid) and the direct sums near f = 0 run on the
+  // auxiliary stream, beside the f geometry, and join before the second pass.
+  const bool fork = a.periodogram && aux != nullptr;
+  hipStream_t s2 = fork ? aux->s : s;
+  auto mark = [&](int stage, int begin, hipStream_t st) {
+    if (hook) hook->fn(hook->ud, stage, begin, st);
   };
-  mark(kStageStats, 1);
+  mark(kStageStats, 1, s);
   hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
   hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kThreads), 0, s, a, w, kStatsBlocks);
-  if (a.periodogram) {
-    const unsigned lb = grid_for(a.nd, kLowBlocks);
-    hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s, a, w);
-    hipLaunchKernelGGL(k_lowfreq_final, dim3(kLowParts), dim3(kLowFinalThreads), 0, s, a, w,
-                       (int)lb);
-  }
-  mark(kStageStats, 0);
-  mark(kStageBin, 1);
+  mark(kStageStats, 0, s);
+  mark(kStageBin, 1, s);
   const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
   hipLaunchKernelGGL(k_bins_sorted, dim3(grid_for(nbt, 1 << 20)), dim3(kThreads), 0, s, a, p, w);
   // counting-sort path: these exit at once unless a descent was found
@@ -521,12 +520,33 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   hipLaunchKernelGGL(k_scan1, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
   hipLaunchKernelGGL(k_scan3, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
   hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
-  mark(kStageBin, 0);
+  mark(kStageBin, 0, s);
+  if (fork) {
+    hipError_t e = hipEventRecord(aux->fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, aux->fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  if (a.periodogram) {
+    mark(kStageLow, 1, s2);
+    const unsigned lb = grid_for(a.nd, kLowBlocks);
+    hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s2, a, w);
+    hipLaunchKernelGGL(k_lowfreq_final, dim3(kLowParts), dim3(kLowFinalThreads), 0, s2, a, w,
+                       (int)lb);
+    mark(kStageLow, 0, s2);
+  }
 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
   const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
   const int nd = (int)a.nd;
-  mark(kStageSpreadF, 1);
+  if (a.periodogram) {
+    mark(kStageSpread2F, 1, s2);
+    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd, w.rowflag_2f,
+                       w.act_rows_2f, 1);
+    hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w, 2,
+                       w.act_rows_2f, 1);
+    mark(kStageSpread2F, 0, s2);
+  }
+  mark(kStageSpreadF, 1, s);
   hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
                      w.act_rows_f, 0);
   if (a.periodogram)
@@ -535,51 +555,64 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   else
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
                        w.act_rows_f, 0);
-  mark(kStageSpreadF, 0);
-  if (a.periodogram) {
-    mark(kStageSpread2F, 1);
-    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
-                       w.act_rows_2f, 1);
-    hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 2,
-                       w.act_rows_2f, 1);
-    mark(kStageSpread2F, 0);
-  }
+  mark(kStageSpreadF, 0, s);
   const T2* tw = reinterpret_cast<const T2*>(w.tw);
-  // passes 0 .. npass-2
+  // passes 0 .. npass-2; launch over grids [g0, g0 + ng) of the current set
   T2* cur[3];
   T2* alt[3];
   for (int g = 0; g < 3; ++g) {
     cur[g] = reinterpret_cast<T2*>(w.grid[g]);
     alt[g] = reinterpret_cast<T2*>(w.grid2[g]);
   }
-  for (int ip = 0; ip + 1 < p.npass; ++ip) {
+  auto pass = [&](int ip, int g0, int ng, hipStream_t st) {
     const FftPass& ps = p.pass[ip];
     PassBufs<Real> b;
-    for (int g = 0; g < 3; ++g) {
-      b.in[g] = cur[g];
-      b.out[g] = (ip == 0) ? cur[g] : alt[g];
-      b.rowflag[g] = (ip == 0) ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
+    for (int i = 0; i < 3; ++i) {
+      const int g = g0 + i < 3 ? g0 + i : 2;
+      b.in[i] = cur[g];
+      b.out[i] = (ip == 0) ? cur[g] : alt[g];
+      b.rowflag[i] = (ip == 0) ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
     }
     const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
     const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
     const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ntw) + (size_t)ps.L + 16;
-    mark(kStagePass0 + ip, 1);
     if (ps.big) {
       auto kern = k_fft_pass<Real, EBIG, kThreadsBig, true>;
       big_lds(reinterpret_cast<const void*>(kern), lds);
-      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, G), dim3(kThreadsBig), lds, s, b, ps, tw,
+      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, ng), dim3(kThreadsBig), lds, st, b, ps, tw,
                          w.stats);
     } else {
-      hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads, false>), dim3((unsigned)nblk, G),
-                         dim3(kThreads), lds, s, b, ps, tw, w.stats);
+      hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads, false>), dim3((unsigned)nblk, ng),
+                         dim3(kThreads), lds, st, b, ps, tw, w.stats);
     }
-    mark(kStagePass0 + ip, 0);
-    if (ip > 0) {
-      for (int g = 0; g < 3; ++g) {
-        T2* tmp = cur[g];
-        cur[g] = alt[g];
-        alt[g] = tmp;
-      }
+  };
+  if (p.npass >= 2) {
+    if (fork) {
+      mark(kStagePass0, 1, s2);
+      pass(0, 2, 1, s2);  // 2f grid
+      mark(kStagePass0, 0, s2);
+      mark(kStagePass0, 1, s);
+      pass(0, 0, 2, s);   // f grids
+      mark(kStagePass0, 0, s);
+    } else {
+      mark(kStagePass0, 1, s);
+      pass(0, 0, G, s);
+      mark(kStagePass0, 0, s);
+    }
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(aux->join, s2);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, aux->join, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (int ip = 1; ip + 1 < p.npass; ++ip) {
+    mark(kStagePass0 + ip, 1, s);
+    pass(ip, 0, G, s);
+    mark(kStagePass0 + ip, 0, s);
+    for (int g = 0; g < 3; ++g) {
+      T2* tmp = cur[g];
+      cur[g] = alt[g];
+      alt[g] = tmp;
     }
   }
   {
@@ -593,7 +626,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
     const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
     const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ntw);
-    mark(kStageLast, 1);
+    mark(kStageLast, 1, s);
     if (ps.big) {
       auto kern = a.periodogram ? k_fft_last<Real, 3, EBIG, kThreadsBig, true>
                                 : k_fft_last<Real, 1, EBIG, kThreadsBig, true>;
@@ -609,15 +642,15 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
                          dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
                          w.lowfix);
     }
-    mark(kStageLast, 0);
+    mark(kStageLast, 0, s);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
-                       const StageHook* hook) {
-  if (p.prec == 1) return launch_path_t<float>(a, p, w, s, hook);
-  return launch_path_t<double>(a, p, w, s, hook);
+                       const StageHook* hook, const AuxStream* aux) {
+  if (p.prec == 1) return launch_path_t<float>(a, p, w, s, hook, aux);
+  return launch_path_t<double>(a, p, w, s, hook, aux);
 }
 
 }  // namespace mils

@@ -126,7 +126,7 @@ SIGNATURES = {
     "mils_server_destroy": ([_P], ctypes.c_int),
 }
 
-MILS_NUM_STAGES = 8
+MILS_NUM_STAGES = 9
 
 
 def load():
