@@ -310,7 +310,8 @@ __global__ __launch_bounds__(NT) void k_bpass(BatchArgs ba, const BatchItem* ite
 // The last pass with deconvolution, crop and power: one workgroup per
 // (series, row block).
 template <typename Real>
-__global__ __launch_bounds__(kThreadsLast) void k_blast(BatchArgs ba, const BatchItem* items) {
+__global__ __launch_bounds__(last_threads<Real>()) void k_blast(BatchArgs ba,
+                                                               const BatchItem* items) {
   using T2 = typename cplx<Real>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int ELAST = sizeof(Real) == 8 ? kElast64 : kElast32;
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(kThreadsLast) void k_blast(BatchArgs ba, const Batc
     b.out[g] = nullptr;
     b.rowflag[g] = nullptr;
   }
-  fft_last_block<Real, 3, ELAST, kThreadsLast>(it.sub, b, ps, n, c.nf, c.K, a,
+  fft_last_block<Real, 3, ELAST, last_threads<Real>()>(it.sub, b, ps, n, c.nf, c.K, a,
                                                reinterpret_cast<const T2*>(ba.tw[c.plan]),
                                                ba.inv_phihat[c.plan], st, smem, w.lowfix, 1);
 }
@@ -352,8 +353,8 @@ hipError_t launch_t(const BatchLaunch& bl, hipStream_t s) {
       hipLaunchKernelGGL(k_bpass<Real>, dim3(bl.npass_items[ip]), dim3(NT), bl.pass_lds[ip], s,
                          ba, bl.pass_items[ip], ip);
   if (bl.nlast > 0)
-    hipLaunchKernelGGL(k_blast<Real>, dim3(bl.nlast), dim3(kThreadsLast), bl.last_lds, s, ba,
-                       bl.last_items);
+    hipLaunchKernelGGL(k_blast<Real>, dim3(bl.nlast), dim3(last_threads<Real>()), bl.last_lds, s,
+                       ba, bl.last_items);
   return hipGetLastError();
 }
 

@@ -496,6 +496,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   constexpr bool f64 = sizeof(Real) == 8;
   constexpr int EMID = f64 ? kEmid64 : kEmid32;
   constexpr int ELAST = f64 ? kElast64 : kElast32;
+  constexpr int NTL = last_threads<Real>();
   constexpr int EBIG = f64 ? kEbig64 : kEbig32;
   const int G = a.periodogram ? 3 : 1;
   // The periodogram forks after binning: the 2f geometry (row flags, spread,
@@ -634,12 +635,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreadsBig), lds, s, b, ps, p, a, tw,
                          w.inv_phihat, w.stats, w.lowfix);
     } else if (a.periodogram) {
-      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, kThreadsLast, false>), dim3((unsigned)nblk),
-                         dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
+      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, NTL, false>), dim3((unsigned)nblk),
+                         dim3(NTL), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
                          w.lowfix);
     } else {
-      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, kThreadsLast, false>), dim3((unsigned)nblk),
-                         dim3(kThreadsLast), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
+      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, NTL, false>), dim3((unsigned)nblk),
+                         dim3(NTL), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
                          w.lowfix);
     }
     mark(kStageLast, 0, s);

@@ -125,7 +125,13 @@ struct Work {
 
 constexpr int kStatsBlocks = 1024;
 constexpr int kThreads = 256;       // threads of most kernels
-constexpr int kThreadsLast = 512;   // threads of the last FFT pass
+// threads of the last FFT pass: FP64 blocks hold 4 rows of each grid, FP32
+// blocks 8 (the radix-16 stages then keep most threads busy in both)
+constexpr int kThreadsLast64 = 256, kThreadsLast32 = 512;
+template <typename Real>
+constexpr int last_threads() {
+  return sizeof(Real) == 8 ? kThreadsLast64 : kThreadsLast32;
+}
 // Big passes: one workgroup of kThreadsBig threads per CU holds a column (or
 // row) set of up to kEbig elements in LDS, so that two passes cover grids of
 // ~1e7 cells.  Their in-pass twiddles come from a two-level table in LDS:
