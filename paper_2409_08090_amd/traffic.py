@@ -12,7 +12,7 @@ FETCH_SIZE / WRITE_SIZE are read in KiB per dispatch.  Each is scaled by the
 ratio between the bytes a plain device copy of known size moves (read once,
 written once; bench.py --calibrate-copy runs one of 2^30 bytes) and what the
 same counter reads for that copy.  Dispatches of the periodogram are named by
-their stage; the two FFT pass launches of a step are told apart by order.
+their stage and summed per periodogram (the first FFT pass is two launches).
 """
 from __future__ import annotations
 
@@ -26,9 +26,9 @@ from collections import defaultdict
 
 COPY_BYTES = 1 << 30
 STAGE_OF = [
-    ("k_stats", "stats"), ("k_lowfreq", "stats"), ("k_bins_sorted", "bin_sort"),
-    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_spread", None),
-    ("k_fft_pass", None), ("k_fft_last", "fft_last_power"),
+    ("k_stats", "stats"), ("k_lowfreq", "lowfreq"), ("k_bins_sorted", "bin_sort"),
+    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_row_class<2>", "spread_2f"),
+    ("k_row_class<1>", "spread_f"), ("k_fft_last", "fft_last_power"),
 ]
 
 
@@ -56,29 +56,47 @@ def per_dispatch(d, counter):
     return [(k, names[k], acc[k]) for k in sorted(acc)]
 
 
+def _is_2f(name):
+    return "Li2ELi1E" in name or "<double, 2, 1>" in name or "<float, 2, 1>" in name
+
+
 def stage_bytes(disp, scale):
-    """Average scaled bytes per launch of each stage of the last full step."""
-    per = defaultdict(list)
-    pass_idx = 0
+    """Average scaled bytes per periodogram of each stage, over the complete
+    periodograms in the trace (each starts with k_stats).  A periodogram
+    launches the first FFT pass twice (the 2f grid, then the two f grids,
+    after the 2f spread): those two make stage fft_pass_0, and the i-th
+    later pass launch is fft_pass_i."""
+    steps = []
+    cur = None
+    npass = 0
+    fork = False
     for _, name, kib in disp:
+        if "k_stats" in name and "k_stats_final" not in name:
+            cur = defaultdict(float)
+            steps.append(cur)
+            npass = 0
+            fork = False
+        if cur is None:
+            continue
         stage = None
         if "k_spread" in name:
-            stage = "spread_2f" if "Li2ELi1E" in name or "<double, 2, 1>" in name or \
-                "<float, 2, 1>" in name else "spread_f"
+            fork = fork or _is_2f(name)
+            stage = "spread_2f" if _is_2f(name) else "spread_f"
         elif "k_fft_pass" in name:
-            stage = f"fft_pass_{pass_idx}"
-            pass_idx += 1
-        elif "k_fft_last" in name:
-            stage = "fft_last_power"
-            pass_idx = 0
+            stage = f"fft_pass_{max(0, npass - 1) if fork else npass}"
+            npass += 1
         else:
             for key, st in STAGE_OF:
-                if key in name and st:
+                if key in name:
                     stage = st
                     break
         if stage:
-            per[stage].append(kib * 1024.0 * scale)
-    return {k: sum(v) / len(v) for k, v in per.items()}
+            cur[stage] += kib * 1024.0 * scale
+    done = [st for st in steps if "fft_last_power" in st]
+    if not done:
+        return {}
+    keys = set().union(*done)
+    return {k: sum(st.get(k, 0.0) for st in done) / len(done) for k in keys}
 
 
 def copy_scale(disp):
@@ -89,14 +107,20 @@ def copy_scale(disp):
     return (COPY_BYTES / 1024.0) / kib if kib > 0 else None
 
 
+# The sources the single-series kernels are compiled from, and the planner
+# that fixes their launch shapes: a change to any of them makes stored
+# counter readings stale.
+SINGLE_PATH_SOURCES = ("device_math.h", "fft_core.h", "kernels.h", "kernels.hip",
+                       "mils_internal.h", "path_device.h", "plan.cpp", "plan.h")
+
+
 def kernel_source_hash(root):
     h = hashlib.sha256()
     csrc = os.path.join(root, "paper_2409_08090_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        if fn.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, fn), "rb") as f:
-                h.update(fn.encode())
-                h.update(f.read())
+    for fn in SINGLE_PATH_SOURCES:
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

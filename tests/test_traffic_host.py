@@ -1,0 +1,46 @@
+"""Host logic of the counter summary (paper_2409_08090_amd.traffic): which
+dispatch of a periodogram counts toward which stage, on a synthetic trace."""
+from paper_2409_08090_amd import traffic
+
+
+def _step(scale=1.0):
+    names = [
+        ("void mils::k_stats(mils::CallArgs, mils::Work)", 1),
+        ("void mils::k_stats_final(mils::CallArgs, mils::Work, int)", 1),
+        ("void mils::k_bins_sorted(mils::CallArgs, mils::Plan, mils::Work)", 2),
+        ("void mils::k_lowfreq(mils::CallArgs, mils::Work)", 3),
+        ("void mils::k_lowfreq_final(mils::CallArgs, mils::Work, int)", 1),
+        ("void mils::k_row_class<2>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_spread_rows<double, 2, 1>(mils::CallArgs, mils::Plan, mils::Work)", 5),
+        ("void mils::k_row_class<1>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_spread_rows<double, 1, 2>(mils::CallArgs, mils::Plan, mils::Work)", 7),
+        ("void mils::k_fft_pass<double, 2048, 256, false>(...)", 11),   # first pass, 2f grid
+        ("void mils::k_fft_pass<double, 2048, 256, false>(...)", 13),   # first pass, f grids
+        ("void mils::k_fft_pass<double, 2048, 256, false>(...)", 17),   # middle pass
+        ("void mils::k_fft_last<double, 3, 3072, 256, false>(...)", 19),
+    ]
+    return [(0, n, k * scale) for n, k in names]
+
+
+def test_stage_bytes_per_periodogram():
+    disp = [(0, "void mils::k_phihat(...)", 100.0)] + _step() + _step(3.0)
+    got = traffic.stage_bytes(disp, 1.0 / 1024.0)
+    # the average of the two periodograms (scales 1 and 3)
+    want = {"stats": 2, "bin_sort": 2, "lowfreq": 4, "spread_2f": 6, "spread_f": 8,
+            "fft_pass_0": 24, "fft_pass_1": 17, "fft_last_power": 19}
+    assert set(got) == set(want)
+    for k, v in want.items():
+        assert abs(got[k] - 2.0 * v) < 1e-9, k
+
+
+def test_incomplete_periodogram_is_ignored():
+    disp = _step() + _step(5.0)[:6]
+    got = traffic.stage_bytes(disp, 1.0 / 1024.0)
+    assert abs(got["fft_pass_1"] - 17.0) < 1e-9
+    assert abs(got["stats"] - 2.0) < 1e-9
+
+
+def test_copy_scale():
+    disp = [(0, "__amd_rocclr_copyBuffer", traffic.COPY_BYTES / 1024.0 / 2.0)]
+    assert abs(traffic.copy_scale(disp) - 2.0) < 1e-12
+    assert traffic.copy_scale([(0, "k_stats", 1.0)]) is None
