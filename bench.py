@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-shared", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one device copy of 2^30 bytes (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
@@ -204,6 +205,31 @@ def main():
             bms = (time.perf_counter() - b0) * 1e3 / nb
             extra["batch"][prec] = {"ms_per_batch": round(bms, 3),
                                     "value": bsums / (bms * 1e-3), "eps": e}
+
+    # shared observation times: 8 series on the large curve's times, one dy
+    # row for all (the weight-only sums run once), FP64 and FP32
+    if not args.no_shared and not args.no_extra:
+        sh = workloads.shared_times(seed=5, nd=c.nd, nseries=8)
+        st_t, st_y, st_dy = to(sh.t), to(sh.y), to(sh.dy[0])
+        sout = torch.empty((sh.nseries, sh.nf), dtype=torch.float64, device=dev)
+        ssums = float(sh.nseries) * float(sh.nd) * float(sh.nf)
+        extra["shared_times"] = {"nseries": sh.nseries, "nd": sh.nd, "nf": sh.nf}
+        for prec, e in (("fp64", 1e-9), ("fp32", 1e-5)):
+            for _ in range(2):
+                mils.periodogram_shared_t(st_t, st_y, st_dy, sh.f0, sh.df, sh.nf, eps=e,
+                                          precision=prec, out=sout, ctx=ctx, stream=stream)
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            nrep = max(3, args.steps // 4)
+            for _ in range(nrep):
+                mils.periodogram_shared_t(st_t, st_y, st_dy, sh.f0, sh.df, sh.nf, eps=e,
+                                          precision=prec, out=sout, ctx=ctx, stream=stream)
+            torch.cuda.synchronize()
+            hms = (time.perf_counter() - h0) * 1e3 / nrep
+            extra["shared_times"][prec] = {"ms_per_call": round(hms, 3),
+                                           "ms_per_series": round(hms / sh.nseries, 4),
+                                           "value": ssums / (hms * 1e-3), "eps": e}
+        del st_t, st_y, st_dy, sout
 
     # serving: open-loop Poisson arrivals at 2000 requests/s of mixed sizes and
     # precisions (a pool of 192 synthetic curves with N_d log-uniform in

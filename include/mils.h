@@ -180,6 +180,33 @@ int mils_periodogram_async(mils_context *ctx, const double *t, const double *y,
 int mils_context_status(mils_context *ctx);
 
 /*
+ * Periodograms of nseries series observed at the same times (the batched
+ * mode for series sharing their observation times, Sec. 3.1 of the paper).
+ * t: nd doubles; y: nseries x nd doubles, series i at y + i*nd; power:
+ * nseries x p->nf doubles, series i at power + i*p->nf (all device arrays).
+ * dy is NULL (unit weights), one array of nd doubles shared by every series
+ * (dy_stride = 0), or nseries x nd doubles (dy_stride = nd).  Every series
+ * gets exactly the result of mils_periodogram on its own (t, y_i, dy_i).
+ * With shared weights (dy NULL or dy_stride = 0) the weight-only sums
+ * B = sum w^ e^{iwt} at f and B2 at 2f are the same for every series: they
+ * run once, and each series adds its own A = sum w^ y~ e^{iwt} through one
+ * grid; series go in groups of three, whose grids share the FFT launches
+ * and one last pass that reads B and B2 once for the group.  With
+ * per-series weights every series runs the whole path.  Everything runs on
+ * hip_stream (and the context's second stream); the workspace holds the
+ * single-series layout plus 32 bytes per frequency.  Many short series are
+ * better served by mils_periodogram_batch.  status_per_series (host, nullable, nseries int32)
+ * receives each series' status.  Synchronous; returns MILS_OK when every
+ * series succeeded, else the status of the first that did not.  Errors:
+ * MILS_ERR_INVALID_ARG (null pointers, nseries outside [1, 2^24], dy_stride
+ * neither 0 nor nd, or any of mils_periodogram's argument errors).
+ */
+int mils_periodogram_shared_t(mils_context *ctx, const double *t, const double *y,
+                              const double *dy, int64_t dy_stride, int64_t nd, int64_t nseries,
+                              const mils_params *p, double *power, int32_t *status_per_series,
+                              void *hip_stream);
+
+/*
  * Batched periodograms: ncurves independent series in CSR layout.  Curve c
  * has points nd_off[c] .. nd_off[c+1]-1 of t, y, dy and writes power
  * nf_off[c] .. nf_off[c+1]-1 at frequencies f0[c] + k df[c].  nd_off, nf_off

@@ -530,6 +530,125 @@ int mils_periodogram(mils_context* ctx, const double* t, const double* y, const 
                     reinterpret_cast<hipStream_t>(hip_stream), true);
 }
 
+int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* y,
+                              const double* dy, int64_t dy_stride, int64_t nd, int64_t nseries,
+                              const mils_params* p, double* power, int32_t* status_per_series,
+                              void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  int rc = mils_check_periodogram_args(t, y, nd, p, power);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
+  if (nseries < 1 || nseries > ((int64_t)1 << 24))
+    return fail(ctx, MILS_ERR_INVALID_ARG, "nseries must be in [1, 2^24]");
+  if (dy && dy_stride != 0 && dy_stride != nd)
+    return fail(ctx, MILS_ERR_INVALID_ARG, "dy_stride must be 0 (shared dy) or nd");
+  if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  PlanEntry* pe = nullptr;
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, true);
+  if (rc != MILS_OK) return rc;
+  const Plan& plan = pe->plan;
+  // workspace: the single-series layout, then B and B2 per output
+  // frequency and one statistics block per series plus one for the weights
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t base = up(layout_work(plan, nd, 3, nullptr, nullptr));
+  const size_t bsum = up(sizeof(double) * 2 * (size_t)p->nf);
+  const size_t nst = (size_t)nseries + 1;
+  const size_t low = up(sizeof(double) * 6 * kLowMax * kLowParts);
+  rc = ensure_workspace(ctx, base + 2 * bsum + 3 * low + up(sizeof(DevStats) * nst));
+  if (rc != MILS_OK) return rc;
+  Work w{};
+  layout_work(plan, nd, 3, ctx->ws, &w);
+  w.tw = pe->tw;
+  w.inv_phihat = pe->inv_phihat;
+  double* bsum_b = reinterpret_cast<double*>(ctx->ws + base);
+  double* bsum_b2 = reinterpret_cast<double*>(ctx->ws + base + bsum);
+  double* lowfix[3];
+  for (int g = 0; g < 3; ++g)
+    lowfix[g] = reinterpret_cast<double*>(ctx->ws + base + 2 * bsum + g * low);
+  DevStats* stats = reinterpret_cast<DevStats*>(ctx->ws + base + 2 * bsum + 3 * low);
+
+  CallArgs a{};
+  a.t = t;
+  a.dy = dy;
+  a.nd = nd;
+  a.nf = p->nf;
+  a.f0 = p->f0;
+  a.df = p->df;
+  centre_frequency(p->f0, p->df, plan.K, &a.fch, &a.fcl);
+  a.kzero = zero_index(p->f0, p->df, p->nf);
+  a.norm = p->normalization;
+  a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
+  a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.periodogram = 1;
+  const bool shared_w = (dy == nullptr || dy_stride == 0);
+  if (shared_w) {
+    // the weight-only sums B and B2, once
+    CallArgs aw = a;
+    aw.unit_y = 1;
+    Work ww = w;
+    ww.stats = stats + nseries;
+    he = launch_weight_sums(aw, plan, ww, bsum_b, bsum_b2, stream);
+    a.bsum_b = bsum_b;
+    a.bsum_b2 = bsum_b2;
+    a.wstats = ww.stats;
+    // then groups of up to three series: their A grids go through the FFT
+    // passes together and one last pass reads B and B2 once for the group
+    // (one series per group with the optional two-pass FFT)
+    bool big = false;
+    for (int i = 0; i < plan.npass; ++i) big = big || plan.pass[i].big;
+    const int64_t gmax = big ? 1 : 3;
+    // the sort decision of the weights-only call: series need their own
+    // binning only when the points go through the counting sort
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(ctx->host_status, &ww.stats->need_sort, sizeof(int),
+                          hipMemcpyDeviceToHost, stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(stream);
+    const int need_sort = he == hipSuccess ? *ctx->host_status : 1;
+    for (int64_t i0 = 0; i0 < nseries && he == hipSuccess; i0 += gmax) {
+      SeriesGroup sg{};
+      sg.m = (int)std::min<int64_t>(gmax, nseries - i0);
+      sg.need_sort = need_sort;
+      for (int g = 0; g < sg.m; ++g) {
+        sg.y[g] = y + (i0 + g) * nd;
+        sg.power[g] = power + (i0 + g) * p->nf;
+        sg.stats[g] = stats + i0 + g;
+        sg.lowfix[g] = lowfix[g];
+      }
+      he = launch_series_group(a, plan, ww, sg, stream);
+    }
+  } else {
+    AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
+    for (int64_t i = 0; i < nseries && he == hipSuccess; ++i) {
+      CallArgs as = a;
+      as.y = y + i * nd;
+      as.dy = dy + i * nd;
+      as.power = power + i * p->nf;
+      Work ws = w;
+      ws.stats = stats + i;
+      he = launch_path(as, plan, ws, stream, nullptr, ctx->aux ? &aux : nullptr);
+    }
+  }
+  if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+  std::vector<DevStats> host(nst);
+  he = hipMemcpyAsync(host.data(), stats, sizeof(DevStats) * nst, hipMemcpyDeviceToHost, stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(stream);
+  if (he != hipSuccess) return hip_fail(ctx, he, "status readback");
+  ctx->have_pending = false;
+  int first = MILS_OK;
+  for (int64_t i = 0; i < nseries; ++i) {
+    const int st = host[i].status;
+    const int code = st == -1 ? MILS_ERR_INVALID_ARG : st == -2 ? MILS_ERR_DEGENERATE : MILS_OK;
+    if (status_per_series) status_per_series[i] = code;
+    if (first == MILS_OK && code != MILS_OK) first = code;
+  }
+  if (first == MILS_ERR_INVALID_ARG) return fail(ctx, first, "non-finite input or dy <= 0");
+  if (first == MILS_ERR_DEGENERATE) return fail(ctx, first, "constant data: zero reference chi^2");
+  return MILS_OK;
+}
+
 }  // extern "C"
 
 int mils_check_params(const mils_params* p, int64_t nd) {

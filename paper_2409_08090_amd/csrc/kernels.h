@@ -39,6 +39,29 @@ hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStrea
                        const StageHook* hook = nullptr, const AuxStream* aux = nullptr);
 
 // 1 / phihat(m) for m = 0..K by Gauss-Legendre quadrature of the kernel.
+// Series that share their observation times and weights: the weights-only
+// call aw (y == NULL, unit_y set; statistics into w.stats) leaves the
+// deconvolved sums B and B2 of every output frequency in bsum_b and bsum_b2
+// (interleaved re/im), and the binning and row lists in w.
+hipError_t launch_weight_sums(const CallArgs& aw, const Plan& p, const Work& w, double* bsum_b,
+                              double* bsum_b2, hipStream_t s);
+
+// Up to three such series at once: series g has values y[g], writes power[g]
+// and keeps its statistics in stats[g] and its direct sums near f = 0 in
+// lowfix[g]; its A sums go through grid g of the workspace.
+struct SeriesGroup {
+  int m;
+  int need_sort;  // the weights-only call's sort decision (read back by the host)
+  const double* y[3];
+  double* power[3];
+  DevStats* stats[3];
+  double* lowfix[3];
+};
+// a: the call's arguments with bsum_b, bsum_b2 and wstats set; w: the
+// workspace of the weights-only call (w.stats its statistics).
+hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
+                               const SeriesGroup& sg, hipStream_t s);
+
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
                          const double* gphi, int q, hipStream_t s);
 

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(CallArgs a, Work w) {
   const double* yv = a.periodogram ? a.y : a.h;
   for (int64_t j = (int64_t)blockIdx.x * kThreads + tid; j < a.nd; j += (int64_t)gridDim.x * kThreads) {
     double t = a.t[j];
-    double y = yv[j];
+    double y = yv ? yv[j] : 0.0;
     double wj = 1.0;
     if (a.dy) {
       double d = a.dy[j];
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, in
     st->tmax = r.hi;
     st->invalid = r.bad;
     st->unsorted = r.uns;
-    st->need_sort = r.uns;
+    st->need_sort = a.wstats ? a.wstats->need_sort : r.uns;
     st->tau = a.periodogram ? r.lo : 0.0;
     const double W = r.m.W;
     st->ysub = a.center ? r.m.mu : 0.0;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, in
     st->YY = YY;
     int status = 0;
     if (r.bad) status = -1;
-    else if (a.periodogram && !(YY > 0.0)) status = -2;
+    else if (a.periodogram && a.y && !(YY > 0.0)) status = -2;
     st->status = status;
     st->nlow = 0;
     st->k_lo = 0;
@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, in
 __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Work w) {
   const DevStats* st = w.stats;
   if (st->status != 0) return;
+  if (a.wstats && !st->need_sort) return;  // the weights-only call's bins hold
   const int nd = (int)a.nd;
   const int nb = (int)p.nbins;
   // The histogram of the counting sort is cleared by every block, before any
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
     if (pos < 0 || pos >= a.nd) continue;  // cannot happen with a consistent histogram
     w.ts[pos] = t;
     if (a.periodogram) {
-      w.ys[pos] = a.y[j];
+      w.ys[pos] = a.y ? a.y[j] : 0.0;
       w.dys[pos] = a.dy ? a.dy[j] : 1.0;
     } else {
       w.hs[pos] = a.h[j];
@@ -366,6 +367,22 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
   const DevStats st = *stp;
   fft_last_block<Real, G, EMAX, NT, TW2>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat, st,
                                          smem, G == 3 ? lowfix : nullptr, kLowParts);
+}
+
+// The last pass for a group of series sharing their weights (a.nser grids of
+// A sums).  Workgroups of 512 threads are held to 128 registers, so that two
+// of them share a CU.
+template <typename Real, int G, int EMAX, int NT, bool TW2>
+__global__ __launch_bounds__(NT, NT >= 512 ? 4 : 1) void k_fft_last_ser(
+    PassBufs<Real> b, FftPass ps, Plan pl, CallArgs a, const typename cplx<Real>::T* tw,
+    const double* inv_phihat, const DevStats* stp, const double* lowfix) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (stp->status != 0) return;
+  const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
+  const int64_t blk = xcd_remap(blockIdx.x, nblk);
+  const DevStats st = *stp;
+  fft_last_block<Real, G, EMAX, NT, TW2, true>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat,
+                                               st, smem, nullptr, kLowParts);
 }
 
 // Direct FP64 sums A, B, B2 at the (at most kLowMax) frequencies nearest
@@ -489,15 +506,148 @@ hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, cons
   return hipGetLastError();
 }
 
+// Statistics of the call (k_stats + k_stats_final into w.stats).
+static void enqueue_stats(const CallArgs& a, const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
+  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kThreads), 0, s, a, w, kStatsBlocks);
+}
+
+// Binning: the sorted fast path, then the counting sort, whose kernels exit
+// at once unless the fast path found a descent.
+static void enqueue_bins(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s) {
+  const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
+  hipLaunchKernelGGL(k_bins_sorted, dim3(grid_for(nbt, 1 << 20)), dim3(kThreads), 0, s, a, p, w);
+  const unsigned sort_blocks = grid_for(a.nd > p.nbins ? a.nd : p.nbins, 512);
+  hipLaunchKernelGGL(k_sort_hist, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
+  const int64_t nchunks = (p.nbins + 1 + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan1, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
+  hipLaunchKernelGGL(k_scan3, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
+}
+
+// Direct sums near f = 0 into w.lowfix.
+static void enqueue_lowfreq(const CallArgs& a, const Work& w, hipStream_t s) {
+  const unsigned lb = grid_for(a.nd, kLowBlocks);
+  hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s, a, w);
+  hipLaunchKernelGGL(k_lowfreq_final, dim3(kLowParts), dim3(kLowFinalThreads), 0, s, a, w,
+                     (int)lb);
+}
+
+// One first/middle FFT pass over ng grids of b.
+template <typename Real>
+static void enqueue_pass(const FftPass& ps, const PassBufs<Real>& b, int ng, const Work& w,
+                         hipStream_t st) {
+  using T2 = typename cplx<Real>::T;
+  constexpr bool f64 = sizeof(Real) == 8;
+  constexpr int EMID = f64 ? kEmid64 : kEmid32;
+  constexpr int EBIG = f64 ? kEbig64 : kEbig32;
+  const T2* tw = reinterpret_cast<const T2*>(w.tw);
+  const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
+  const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
+  const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ntw) + (size_t)ps.L + 16;
+  if (ps.big) {
+    auto kern = k_fft_pass<Real, EBIG, kThreadsBig, true>;
+    big_lds(reinterpret_cast<const void*>(kern), lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblk, ng), dim3(kThreadsBig), lds, st, b, ps, tw,
+                       w.stats);
+  } else {
+    hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads, false>), dim3((unsigned)nblk, ng),
+                       dim3(kThreads), lds, st, b, ps, tw, w.stats);
+  }
+}
+
+// The last FFT pass over G grids of b: with power (G = 3, or G = 1 for a
+// series sharing its weights), or the complex sums (G = 1).
+template <typename Real>
+static void enqueue_last(const CallArgs& a, const Plan& p, const PassBufs<Real>& b, int G,
+                         const Work& w, hipStream_t s) {
+  using T2 = typename cplx<Real>::T;
+  constexpr bool f64 = sizeof(Real) == 8;
+  constexpr int ELAST = f64 ? kElast64 : kElast32;
+  constexpr int EBIG = f64 ? kEbig64 : kEbig32;
+  constexpr int NTL = last_threads<Real>();
+  const T2* tw = reinterpret_cast<const T2*>(w.tw);
+  const FftPass& ps = p.pass[p.npass - 1];
+  const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
+  const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
+  const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ntw);
+  const dim3 grid((unsigned)nblk);
+  const auto* ip = w.inv_phihat;
+  if (a.nser > 0) {
+    // a group of series sharing their weights (a plan made for three grids,
+    // so D L <= ELAST / 3): grid g holds series g's A sums
+    if (ps.big) {
+      auto kern = k_fft_last_ser<Real, 1, EBIG, kThreadsBig, true>;
+      big_lds(reinterpret_cast<const void*>(kern), lds);
+      hipLaunchKernelGGL(kern, grid, dim3(kThreadsBig), lds, s, b, ps, p, a, tw, ip, w.stats,
+                         w.lowfix);
+    } else if (G == 3) {
+      hipLaunchKernelGGL((k_fft_last_ser<Real, 3, ELAST, NTL, false>), grid, dim3(NTL), lds, s,
+                         b, ps, p, a, tw, ip, w.stats, w.lowfix);
+    } else if (G == 2) {
+      hipLaunchKernelGGL((k_fft_last_ser<Real, 2, 2 * (ELAST / 3), NTL, false>), grid, dim3(NTL),
+                         lds, s, b, ps, p, a, tw, ip, w.stats, w.lowfix);
+    } else {
+      hipLaunchKernelGGL((k_fft_last_ser<Real, 1, ELAST / 3, NTL, false>), grid, dim3(NTL), lds,
+                         s, b, ps, p, a, tw, ip, w.stats, w.lowfix);
+    }
+  } else if (ps.big) {
+    auto kern = G == 3 ? k_fft_last<Real, 3, EBIG, kThreadsBig, true>
+                       : k_fft_last<Real, 1, EBIG, kThreadsBig, true>;
+    big_lds(reinterpret_cast<const void*>(kern), lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreadsBig), lds, s, b, ps, p, a, tw, ip, w.stats,
+                       w.lowfix);
+  } else if (G == 3) {
+    hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, NTL, false>), grid, dim3(NTL), lds, s, b, ps,
+                       p, a, tw, ip, w.stats, w.lowfix);
+  } else if (ps.C * ps.L <= ELAST / 3) {
+    // one grid of a plan made for three (the weight-only sums): the
+    // third-size instance holds a third of the registers
+    hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST / 3, NTL, false>), grid, dim3(NTL), lds, s, b,
+                       ps, p, a, tw, ip, w.stats, w.lowfix);
+  } else {
+    hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, NTL, false>), grid, dim3(NTL), lds, s, b, ps,
+                       p, a, tw, ip, w.stats, w.lowfix);
+  }
+}
+
+// Grids g0 .. g0+ng-1 of w through every pass but the last: the first pass
+// in place (row flags of their geometry: grid grid_2f is of geometry 2f, the
+// others of geometry f), the middle ones alternating with the second grid
+// set.  in[i] receives where grid g0+i ends up.
+template <typename Real>
+static void enqueue_passes(const Plan& p, const Work& w, int g0, int ng, int grid_2f,
+                           hipStream_t s, typename cplx<Real>::T** in) {
+  using T2 = typename cplx<Real>::T;
+  T2* cur[3];
+  T2* alt[3];
+  for (int i = 0; i < ng; ++i) {
+    cur[i] = reinterpret_cast<T2*>(w.grid[g0 + i]);
+    alt[i] = reinterpret_cast<T2*>(w.grid2[g0 + i]);
+  }
+  for (int ip = 0; ip + 1 < p.npass; ++ip) {
+    PassBufs<Real> b;
+    for (int i = 0; i < 3; ++i) {
+      const int j = i < ng ? i : ng - 1;
+      b.in[i] = cur[j];
+      b.out[i] = ip == 0 ? cur[j] : alt[j];
+      b.rowflag[i] = ip == 0 ? (g0 + j == grid_2f ? w.rowflag_2f : w.rowflag_f) : nullptr;
+    }
+    enqueue_pass<Real>(p.pass[ip], b, ng, w, s);
+    if (ip > 0)
+      for (int i = 0; i < ng; ++i) {
+        T2* tmp = cur[i];
+        cur[i] = alt[i];
+        alt[i] = tmp;
+      }
+  }
+  for (int i = 0; i < ng; ++i) in[i] = cur[i];
+}
+
 template <typename Real>
 static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
                                 const StageHook* hook, const AuxStream* aux) {
   using T2 = typename cplx<Real>::T;
-  constexpr bool f64 = sizeof(Real) == 8;
-  constexpr int EMID = f64 ? kEmid64 : kEmid32;
-  constexpr int ELAST = f64 ? kElast64 : kElast32;
-  constexpr int NTL = last_threads<Real>();
-  constexpr int EBIG = f64 ? kEbig64 : kEbig32;
   const int G = a.periodogram ? 3 : 1;
   // The periodogram forks after binning: the 2f geometry (row flags, spread,
   // first FFT pass of its grid) and the direct sums near f = 0 run on the
@@ -508,19 +658,10 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     if (hook) hook->fn(hook->ud, stage, begin, st);
   };
   mark(kStageStats, 1, s);
-  hipLaunchKernelGGL(k_stats, dim3(kStatsBlocks), dim3(kThreads), 0, s, a, w);
-  hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(kThreads), 0, s, a, w, kStatsBlocks);
+  enqueue_stats(a, w, s);
   mark(kStageStats, 0, s);
   mark(kStageBin, 1, s);
-  const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
-  hipLaunchKernelGGL(k_bins_sorted, dim3(grid_for(nbt, 1 << 20)), dim3(kThreads), 0, s, a, p, w);
-  // counting-sort path: these exit at once unless a descent was found
-  const unsigned sort_blocks = grid_for(a.nd > p.nbins ? a.nd : p.nbins, 512);
-  hipLaunchKernelGGL(k_sort_hist, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
-  const int64_t nchunks = (p.nbins + 1 + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan1, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
-  hipLaunchKernelGGL(k_scan3, dim3((unsigned)nchunks), dim3(kThreads), 0, s, p, w);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
+  enqueue_bins(a, p, w, s);
   mark(kStageBin, 0, s);
   if (fork) {
     hipError_t e = hipEventRecord(aux->fork, s);
@@ -529,10 +670,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   }
   if (a.periodogram) {
     mark(kStageLow, 1, s2);
-    const unsigned lb = grid_for(a.nd, kLowBlocks);
-    hipLaunchKernelGGL(k_lowfreq, dim3(lb), dim3(kThreads), 0, s2, a, w);
-    hipLaunchKernelGGL(k_lowfreq_final, dim3(kLowParts), dim3(kLowFinalThreads), 0, s2, a, w,
-                       (int)lb);
+    enqueue_lowfreq(a, w, s2);
     mark(kStageLow, 0, s2);
   }
 
@@ -557,7 +695,6 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
                        w.act_rows_f, 0);
   mark(kStageSpreadF, 0, s);
-  const T2* tw = reinterpret_cast<const T2*>(w.tw);
   // passes 0 .. npass-2; launch over grids [g0, g0 + ng) of the current set
   T2* cur[3];
   T2* alt[3];
@@ -566,7 +703,6 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     alt[g] = reinterpret_cast<T2*>(w.grid2[g]);
   }
   auto pass = [&](int ip, int g0, int ng, hipStream_t st) {
-    const FftPass& ps = p.pass[ip];
     PassBufs<Real> b;
     for (int i = 0; i < 3; ++i) {
       const int g = g0 + i < 3 ? g0 + i : 2;
@@ -574,18 +710,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       b.out[i] = (ip == 0) ? cur[g] : alt[g];
       b.rowflag[i] = (ip == 0) ? (g == 2 ? w.rowflag_2f : w.rowflag_f) : nullptr;
     }
-    const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-    const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
-    const size_t lds = sizeof(T2) * (size_t)(ps.L * ps.C + ntw) + (size_t)ps.L + 16;
-    if (ps.big) {
-      auto kern = k_fft_pass<Real, EBIG, kThreadsBig, true>;
-      big_lds(reinterpret_cast<const void*>(kern), lds);
-      hipLaunchKernelGGL(kern, dim3((unsigned)nblk, ng), dim3(kThreadsBig), lds, st, b, ps, tw,
-                         w.stats);
-    } else {
-      hipLaunchKernelGGL((k_fft_pass<Real, EMID, kThreads, false>), dim3((unsigned)nblk, ng),
-                         dim3(kThreads), lds, st, b, ps, tw, w.stats);
-    }
+    enqueue_pass<Real>(p.pass[ip], b, ng, w, st);
   };
   if (p.npass >= 2) {
     if (fork) {
@@ -617,32 +742,14 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     }
   }
   {
-    const FftPass& ps = p.pass[p.npass - 1];
     PassBufs<Real> b;
     for (int g = 0; g < 3; ++g) {
       b.in[g] = cur[g];
       b.out[g] = nullptr;
       b.rowflag[g] = nullptr;
     }
-    const int64_t nblk = (ps.P + ps.C - 1) / ps.C;
-    const int ntw = ps.big ? tw2_count(ps.L) : ps.L;
-    const size_t lds = sizeof(T2) * (size_t)(ps.L * last_pitch(G * ps.C) + ntw);
     mark(kStageLast, 1, s);
-    if (ps.big) {
-      auto kern = a.periodogram ? k_fft_last<Real, 3, EBIG, kThreadsBig, true>
-                                : k_fft_last<Real, 1, EBIG, kThreadsBig, true>;
-      big_lds(reinterpret_cast<const void*>(kern), lds);
-      hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreadsBig), lds, s, b, ps, p, a, tw,
-                         w.inv_phihat, w.stats, w.lowfix);
-    } else if (a.periodogram) {
-      hipLaunchKernelGGL((k_fft_last<Real, 3, ELAST, NTL, false>), dim3((unsigned)nblk),
-                         dim3(NTL), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
-                         w.lowfix);
-    } else {
-      hipLaunchKernelGGL((k_fft_last<Real, 1, ELAST, NTL, false>), dim3((unsigned)nblk),
-                         dim3(NTL), lds, s, b, ps, p, a, tw, w.inv_phihat, w.stats,
-                         w.lowfix);
-    }
+    enqueue_last<Real>(a, p, b, G, w, s);
     mark(kStageLast, 0, s);
   }
   return hipGetLastError();
@@ -652,6 +759,97 @@ hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStrea
                        const StageHook* hook, const AuxStream* aux) {
   if (p.prec == 1) return launch_path_t<float>(a, p, w, s, hook, aux);
   return launch_path_t<double>(a, p, w, s, hook, aux);
+}
+
+// ============================================================================
+// Series sharing their observation times and weights (the batched mode for
+// shared times): B (geometry f) and B2 (geometry 2f) depend on t and the
+// weights only, so they are computed once, and each series adds the sum A
+// through one grid.
+// ============================================================================
+template <typename Real>
+static hipError_t launch_weight_sums_t(const CallArgs& aw, const Plan& p, const Work& w,
+                                       double* bsum_b, double* bsum_b2, hipStream_t s) {
+  using T2 = typename cplx<Real>::T;
+  enqueue_stats(aw, w, s);
+  enqueue_bins(aw, p, w, s);
+  const int64_t ntiles = (p.S1 / p.T) * p.nrows;
+  const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
+  const int nd = (int)aw.nd;
+  hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
+                     w.act_rows_f, 0);
+  hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
+                     w.act_rows_2f, 1);
+  hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, aw, p, w, 1,
+                     w.act_rows_f, 0);
+  hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s, aw, p, w, 2,
+                     w.act_rows_2f, 1);
+  T2* in[2];
+  enqueue_passes<Real>(p, w, 1, 2, 2, s, in);
+  CallArgs as = aw;
+  as.periodogram = 0;  // the last pass writes the deconvolved sums
+  for (int i = 0; i < 2; ++i) {
+    PassBufs<Real> b;
+    for (int g = 0; g < 3; ++g) {
+      b.in[g] = in[i];
+      b.out[g] = nullptr;
+      b.rowflag[g] = nullptr;
+    }
+    as.sums = i == 0 ? bsum_b : bsum_b2;
+    enqueue_last<Real>(as, p, b, 1, w, s);
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
+static hipError_t launch_series_group_t(const CallArgs& a, const Plan& p, const Work& w,
+                                        const SeriesGroup& sg, hipStream_t s) {
+  using T2 = typename cplx<Real>::T;
+  const int64_t ntiles = (p.S1 / p.T) * p.nrows;
+  const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
+  CallArgs al = a;
+  al.nser = sg.m;
+  for (int g = 0; g < sg.m; ++g) {
+    // statistics, binning (only when the points must be sorted: the sorted
+    // copy of y is the series' own; otherwise the weights-only call's bins
+    // hold), direct sums near f = 0, and the A spread into grid g
+    CallArgs ag = a;
+    ag.y = sg.y[g];
+    Work wg = w;
+    wg.stats = sg.stats[g];
+    wg.lowfix = sg.lowfix[g];
+    enqueue_stats(ag, wg, s);
+    if (sg.need_sort) enqueue_bins(ag, p, wg, s);
+    enqueue_lowfreq(ag, wg, s);
+    hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, ag, p, wg,
+                       g, w.act_rows_f, 0);
+    al.spow[g] = sg.power[g];
+    al.sst[g] = sg.stats[g];
+    al.slow[g] = sg.lowfix[g];
+  }
+  T2* in[3];
+  enqueue_passes<Real>(p, w, 0, sg.m, -1, s, in);
+  PassBufs<Real> b;
+  for (int g = 0; g < 3; ++g) {
+    b.in[g] = in[g < sg.m ? g : sg.m - 1];
+    b.out[g] = nullptr;
+    b.rowflag[g] = nullptr;
+  }
+  enqueue_last<Real>(al, p, b, sg.m, w, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_sums(const CallArgs& aw, const Plan& p, const Work& w, double* bsum_b,
+                              double* bsum_b2, hipStream_t s) {
+  if (p.prec == 1) return launch_weight_sums_t<float>(aw, p, w, bsum_b, bsum_b2, s);
+  return launch_weight_sums_t<double>(aw, p, w, bsum_b, bsum_b2, s);
+}
+
+hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
+                               const SeriesGroup& sg, hipStream_t s) {
+  if (sg.m < 1 || sg.m > 3) return hipErrorInvalidValue;
+  if (p.prec == 1) return launch_series_group_t<float>(a, p, w, sg, s);
+  return launch_series_group_t<double>(a, p, w, sg, s);
 }
 
 }  // namespace mils

@@ -96,6 +96,24 @@ struct CallArgs {
   int periodogram;    // 1: three grids + power; 0: one grid + complex sums
   double* power;      // periodogram output
   double* sums;       // trig sums output (interleaved re/im)
+  // Series sharing their weights (same t and dy): a weights-only call has
+  // y == NULL (the statistics then take y = 0 and skip the constant-data
+  // check) and unit_y set (the f-geometry strength is w^ e^{iwt}, the B
+  // sum), and leaves B and B2 per output frequency in bsum_b, bsum_b2
+  // (interleaved re/im, deconvolved).
+  int unit_y;
+  const double* bsum_b;
+  const double* bsum_b2;
+  // A series sharing its times with an earlier weights-only call: that
+  // call's statistics (its sort decision holds for the series, and its bin
+  // starts are still in the workspace unless the points must be sorted).
+  const DevStats* wstats;
+  // Last pass over nser (1..3) such series at once, grid g holding the A
+  // sums of series g: its power, statistics and direct sums near f = 0.
+  int nser;
+  double* spow[3];
+  const DevStats* sst[3];
+  const double* slow[3];
 };
 
 // Device workspace of one call, carved from one allocation.

@@ -235,7 +235,7 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
               }
               const double wh = wj * invW;
               if (GEO == 1) {
-                const double yt = yy[j] - ysub;
+                const double yt = a.unit_y ? 1.0 : yy[j] - ysub;
                 hre[0] = (Real)(wh * yt * pc);
                 him[0] = (Real)(wh * yt * ps);
                 if (NG > 1) {
@@ -432,7 +432,7 @@ __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, doub
 // twiddle table (L entries, or tw2_count(L) for TW2).  nf and K are those of
 // the series (a batched series may use fewer frequencies than its grid's
 // plan).
-template <typename Real, int G, int EMAX, int NT, bool TW2 = false>
+template <typename Real, int G, int EMAX, int NT, bool TW2 = false, bool SER = false>
 __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPass& ps,
                                int64_t n, int64_t nf, int64_t K, const CallArgs& a,
                                const typename cplx<Real>::T* tw, const double* inv_phihat,
@@ -493,6 +493,14 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       }
     }
   }
+  // statistics of the series of a shared-weights group, once per workgroup
+  // (uniform loads; the power stores below cannot then force reloads)
+  DevStats ser[SER ? G : 1];
+  if constexpr (SER) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (g < a.nser) ser[g] = *a.sst[g];
+  }
   lds_fft<EMAX, NT, TW2>(buf, L, G * D, R, ps.rad, ps.nrad, twL);
 #pragma unroll
   for (int i = 0; i < PO; ++i) {
@@ -502,7 +510,30 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
     const int d = e & (D - 1);
     const int k = e >> dsh;
     const double ip = ipv[i];
-    if (G == 3) {
+    if constexpr (SER) {
+      // series sharing their weights: grid g holds series g's A; B and B2
+      // were computed once for all
+      const double2 B = reinterpret_cast<const double2*>(a.bsum_b)[kout];
+      const double2 B2 = reinterpret_cast<const double2*>(a.bsum_b2)[kout];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g >= a.nser) continue;
+        const DevStats& sg = ser[g];
+        if (sg.status != 0) continue;
+        const T2 A = buf[k * R + g * D + d];
+        double s6[6] = {(double)A.x * ip, (double)A.y * ip, B.x, B.y, B2.x, B2.y};
+        const int64_t q = kout - sg.k_lo;
+        if (q >= 0 && q < sg.nlow) {
+          const double* lf = a.slow[g];
+          for (int j = 0; j < 6; ++j) s6[j] = lf[6 * q + j];
+          for (int r = 1; r < lowparts; ++r)
+            for (int j = 0; j < 6; ++j) s6[j] += lf[r * 6 * kLowMax + 6 * q + j];
+        }
+        double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], sg, a.norm, a.fit_mean);
+        if (kout == a.kzero) pw = 0.0;
+        a.spow[g][kout] = pw;
+      }
+    } else if (G == 3) {
       const T2 A = buf[k * R + d];
       const T2 B = buf[k * R + D + d];
       const T2 B2 = buf[k * R + 2 * D + d];

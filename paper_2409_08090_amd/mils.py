@@ -111,6 +111,9 @@ SIGNATURES = {
     "mils_periodogram_batch": ([_P, ctypes.c_int64, _I64P, _P, _P, _P, _I64P, _D, _D,
                                 ctypes.POINTER(mils_params), _P,
                                 ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
+    "mils_periodogram_shared_t": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_int64, ctypes.POINTER(mils_params), _P,
+                                   ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
     "mils_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "mils_profile_stage_name": ([ctypes.c_int], ctypes.c_char_p),
     "mils_profile_read": ([_P, _D, _I64P], ctypes.c_int),
@@ -347,6 +350,42 @@ def periodogram_batch(t, y, dy, nd_off, nf_off, f0, df, eps=1e-9, precision="fp6
         ctx.handle, nc, nd_off.ctypes.data_as(_I64P), ctypes.c_void_p(t.data_ptr()),
         ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(dy.data_ptr()) if dy is not None else None,
         nf_off.ctypes.data_as(_I64P), f0.ctypes.data_as(_D), df.ctypes.data_as(_D),
+        ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+        st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream_ptr(stream))
+    if rc not in (MILS_OK, MILS_ERR_INVALID_ARG, MILS_ERR_DEGENERATE) or not return_status:
+        ctx.check(rc)
+    return (out, st) if return_status else out
+
+
+def periodogram_shared_t(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64",
+                         normalization="standard", center_data=True, fit_mean=True, out=None,
+                         stream=None, ctx=None, return_status=False):
+    """Periodograms of the rows of y (nseries x nd device tensor), all observed
+    at times t (nd).  dy: None, one row of nd shared by every series, or
+    nseries x nd.  Returns an nseries x nf float64 device tensor."""
+    import numpy as np
+    import torch
+    t = _dev_f64(t, "t")
+    y = _dev_f64(y, "y")
+    nd = int(t.numel())
+    if y.dim() != 2 or y.shape[1] != nd:
+        raise ValueError("y must be nseries x nd")
+    ns = int(y.shape[0])
+    stride = 0
+    if dy is not None:
+        dy = _dev_f64(dy, "dy")
+        if dy.dim() == 2 and dy.shape[0] == ns and ns > 1:
+            stride = nd
+        if dy.shape[-1] != nd or (dy.dim() == 2 and dy.shape[0] not in (1, ns)):
+            raise ValueError("dy must be nd, 1 x nd or nseries x nd")
+    if out is None:
+        out = torch.empty((ns, int(nf)), dtype=torch.float64, device=t.device)
+    st = np.zeros(ns, dtype=np.int32)
+    ctx = ctx or default_context(t.device.index)
+    p = make_params(f0, df, nf, eps, precision, normalization, center_data, fit_mean)
+    rc = load().mils_periodogram_shared_t(
+        ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+        ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, stride, nd, ns,
         ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
         st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream_ptr(stream))
     if rc not in (MILS_OK, MILS_ERR_INVALID_ARG, MILS_ERR_DEGENERATE) or not return_status:

@@ -118,6 +118,60 @@ def serving_requests(seed: int = 4, nreq: int = 20_000, rate: float = 2000.0,
     return out
 
 
+@dataclass
+class SharedTimes:
+    """Series observed at the same times: y and dy are nseries x nd (dy rows
+    are identical when the series share their weights)."""
+    t: np.ndarray
+    y: np.ndarray
+    dy: np.ndarray
+    f0: float
+    df: float
+    nf: int
+
+    @property
+    def nd(self) -> int:
+        return int(self.t.size)
+
+    @property
+    def nseries(self) -> int:
+        return int(self.y.shape[0])
+
+    def curve(self, i: int) -> Curve:
+        return Curve(self.t, self.y[i], self.dy[i], self.f0, self.df, self.nf)
+
+
+def shared_times(seed: int = 5, nd: int = 1_000_000, nseries: int = 8, span_years: int = 10,
+                 nf: int | None = None, shared_dy: bool = True,
+                 sorted_t: bool = True) -> SharedTimes:
+    """Several series on the times of the single large curve (10 years with
+    120-day gaps): each row of y is its own mix of three sinusoids
+    (f ~ U[0.01, 5], amplitude ~ U[0.1, 1]) plus N(0, 0.2^2); dy ~ U(0.1, 0.3),
+    one row for every series or (shared_dy False) a row per series;
+    df = 1/(5 span), f0 = df, N_f = 12 N_d.  ``sorted_t`` False returns the
+    same times (and the matching y, dy columns) in a random order."""
+    rng = np.random.default_rng(seed)
+    t = gapped_times(rng, nd, years=span_years)
+    y = np.empty((nseries, nd))
+    for i in range(nseries):
+        fs = rng.uniform(0.01, 5.0, 3)
+        amp = rng.uniform(0.1, 1.0, 3)
+        ph = rng.uniform(0.0, 2 * np.pi, 3)
+        y[i] = rng.normal(0.0, 0.2, nd)
+        for f, a, p in zip(fs, amp, ph):
+            y[i] += a * np.sin(2 * np.pi * f * t + p)
+    if shared_dy:
+        dy = np.broadcast_to(rng.uniform(0.1, 0.3, nd), (nseries, nd)).copy()
+    else:
+        dy = rng.uniform(0.1, 0.3, (nseries, nd))
+    if not sorted_t:
+        perm = rng.permutation(nd)
+        t, y, dy = t[perm], y[:, perm], dy[:, perm]
+    span = 365.0 * span_years
+    df = 1.0 / (5.0 * span)
+    return SharedTimes(t, y, dy, df, df, int(nf if nf is not None else 12 * nd))
+
+
 def uniform_series(seed: int, nd: int, nf: int, span: float = 1.0, sorted_t: bool = True,
                    hetero_dy: bool = True) -> Curve:
     """Generic random series for edge-case tests: uniform times on [0, span],

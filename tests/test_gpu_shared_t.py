@@ -1,0 +1,153 @@
+"""GPU parity of the shared-times form (series observed at the same times,
+the batched mode of Sec. 3.1) against the CPU oracle, through the C ABI
+(mils_periodogram_shared_t).
+
+With shared weights the path computes the weight-only sums B (f) and B2 (2f)
+once and each series' A through one grid; with per-series weights every
+series runs the whole path.  Each series must match the oracle on its own
+(t, y_i, dy_i) to the tolerances of the single-series path:
+  FP64 at eps=1e-9: max|P - P_ref| / max|P_ref| <= 1e-8
+  FP32 at eps=1e-5: max|P - P_ref| / max|P_ref| <= 1e-4
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle  # noqa: E402
+from paper_2409_08090_amd import mils, workloads  # noqa: E402
+
+TOL = {"fp64": 1e-8, "fp32": 1e-4}
+EPS = {"fp64": 1e-9, "fp32": 1e-5}
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def rel_err(p, ref):
+    return np.max(np.abs(p - ref)) / np.max(np.abs(ref))
+
+
+def run(s, precision, dy_mode, **kw):
+    """dy_mode: 'shared' (one row), 'none', or 'series' (a row per series)."""
+    dy = {"shared": lambda: dev(s.dy[0]), "none": lambda: None,
+          "series": lambda: dev(s.dy)}[dy_mode]()
+    out = mils.periodogram_shared_t(dev(s.t), dev(s.y), dy, s.f0, s.df, s.nf,
+                                    eps=EPS[precision], precision=precision, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy() if not isinstance(out, tuple) else (out[0].cpu().numpy(), out[1])
+
+
+def oracle_row(s, i, dy_mode, k=None):
+    dy = None if dy_mode == "none" else s.dy[i]
+    if k is None:
+        return oracle.periodogram(s.t, s.y[i], dy, s.f0, s.df, nf=s.nf)
+    return oracle.periodogram(s.t, s.y[i], dy, s.f0, s.df, k=k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("dy_mode", ["shared", "none", "series"])
+def test_every_series_matches_oracle(precision, dy_mode):
+    s = workloads.shared_times(seed=51, nd=1500, nseries=5, span_years=2,
+                               shared_dy=dy_mode != "series")
+    p = run(s, precision, dy_mode)
+    assert p.shape == (5, s.nf)
+    for i in range(s.nseries):
+        err = rel_err(p[i], oracle_row(s, i, dy_mode))
+        print(f"[shared_t {precision} dy={dy_mode} series {i}] max-normalised {err:.3e}",
+              flush=True)
+        assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_three_pass_plan_sampled(precision):
+    # nf = 4e5 plans three FFT passes in both precisions: the shared B, B2
+    # grids and each series' A grid go through the second grid set
+    s = workloads.shared_times(seed=52, nd=2000, nseries=3, span_years=3, nf=400_000)
+    assert len(mils.plan_info(s.nd, s.nf, EPS[precision], precision, s.f0, s.df)["len"]) == 3
+    p = run(s, precision, "shared")
+    rng = np.random.default_rng(7)
+    for i in range(s.nseries):
+        k = np.unique(np.concatenate([rng.integers(0, s.nf, 300), np.arange(40),
+                                      np.arange(s.nf - 40, s.nf), np.argsort(p[i])[-30:]]))
+        err = rel_err(p[i][k], oracle_row(s, i, "shared", k=k))
+        print(f"[shared_t 3-pass {precision} series {i}] {k.size} frequencies, "
+              f"max-normalised {err:.3e}", flush=True)
+        assert err <= TOL[precision]
+
+
+def test_unsorted_times():
+    s = workloads.shared_times(seed=53, nd=1200, nseries=3, span_years=2, sorted_t=False)
+    p = run(s, "fp64", "shared")
+    for i in range(s.nseries):
+        assert rel_err(p[i], oracle_row(s, i, "shared")) <= 1e-8
+
+
+def test_same_result_as_one_series_calls():
+    s = workloads.shared_times(seed=54, nd=1000, nseries=3, span_years=2)
+    p = run(s, "fp64", "shared")
+    for i in range(s.nseries):
+        q = mils.periodogram(dev(s.t), dev(s.y[i]), dev(s.dy[0]), s.f0, s.df, s.nf, eps=1e-9)
+        q = q.cpu().numpy()
+        # different summation orders of the same sums: far inside the tolerance
+        assert rel_err(p[i], q) <= 1e-11
+
+
+def test_per_series_status():
+    s = workloads.shared_times(seed=55, nd=800, nseries=4, span_years=2)
+    s.y[1] = 3.0            # constant: degenerate
+    s.y[2, 17] = np.nan     # non-finite value
+    p, st = run(s, "fp64", "shared", return_status=True)
+    assert list(st) == [mils.MILS_OK, mils.MILS_ERR_DEGENERATE, mils.MILS_ERR_INVALID_ARG,
+                        mils.MILS_OK]
+    for i in (0, 3):
+        assert rel_err(p[i], oracle_row(s, i, "shared")) <= 1e-8
+    # the call itself reports the first failing series
+    with pytest.raises(mils.MilsError):
+        run(s, "fp64", "shared")
+
+
+def test_invalid_shared_weights_fail_every_series():
+    s = workloads.shared_times(seed=56, nd=500, nseries=3, span_years=2)
+    s.dy[0, 5] = -1.0
+    _, st = run(s, "fp64", "shared", return_status=True)
+    assert list(st) == [mils.MILS_ERR_INVALID_ARG] * 3
+
+
+def test_single_series_and_argument_errors():
+    s = workloads.shared_times(seed=57, nd=600, nseries=1, span_years=2)
+    p = run(s, "fp64", "shared")
+    assert rel_err(p[0], oracle_row(s, 0, "shared")) <= 1e-8
+    with pytest.raises(ValueError):
+        mils.periodogram_shared_t(dev(s.t), dev(s.y[0]), None, s.f0, s.df, s.nf)
+    lib = mils.load()
+    ctx = mils.default_context()
+    prm = mils.make_params(s.f0, s.df, s.nf, 1e-9, "fp64", "standard", True, True)
+    t, y, out = dev(s.t), dev(s.y), torch.empty(s.nf, dtype=torch.float64, device="cuda")
+    import ctypes
+    args = lambda dyp, stride, ns: (ctx.handle, ctypes.c_void_p(t.data_ptr()),  # noqa: E731
+                                    ctypes.c_void_p(y.data_ptr()), dyp, stride, s.nd, ns,
+                                    ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()), None,
+                                    None)
+    assert lib.mils_periodogram_shared_t(*args(None, 0, 0)) == mils.MILS_ERR_INVALID_ARG
+    dyt = dev(s.dy[0])
+    assert lib.mils_periodogram_shared_t(*args(ctypes.c_void_p(dyt.data_ptr()), 7, 1)) == \
+        mils.MILS_ERR_INVALID_ARG
+
+
+def test_large_shared_weights_sampled():
+    # the full-size times (N_d = 1e6, N_f = 1.2e7) with two series
+    s = workloads.shared_times(seed=58, nd=1_000_000, nseries=2)
+    p = run(s, "fp64", "shared")
+    rng = np.random.default_rng(8)
+    for i in range(s.nseries):
+        k = np.unique(np.concatenate([rng.integers(0, s.nf, 120), np.arange(40),
+                                      np.arange(s.nf - 40, s.nf), np.argsort(p[i])[-20:]]))
+        err = rel_err(p[i][k], oracle_row(s, i, "shared", k=k))
+        print(f"[shared_t large series {i}] {k.size} frequencies, max-normalised {err:.3e}",
+              flush=True)
+        assert err <= 1e-8
