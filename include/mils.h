@@ -180,6 +180,29 @@ int mils_periodogram_async(mils_context *ctx, const double *t, const double *y,
 int mils_context_status(mils_context *ctx);
 
 /*
+ * Direct evaluation (Sec. 1, Eq. 1 term by term; the brute-force method the
+ * paper compares with, Sec. 3.1): the same periodogram as mils_periodogram
+ * (same arguments, results and statuses) with every sum accumulated over the
+ * points in FP64 for every frequency -- O(nd * nf) work, no transform, no
+ * approximation beyond FP64 rounding (p->eps and p->precision are ignored).
+ * Per point, the phase at the first of each thread's 12 consecutive
+ * frequencies is reduced in double-double and the next ones follow by
+ * multiplication with exp(2 pi i df (t - t_min)).  Synchronous.  About 5 s
+ * at nd = 1e6, nf = 1.2e7 on one MI355X; a check of the transform path at
+ * any size.
+ */
+int mils_direct_periodogram(mils_context *ctx, const double *t, const double *y,
+                            const double *dy, int64_t nd, const mils_params *p, double *power,
+                            void *hip_stream);
+
+/* Direct raw sums: out[k] = sum_j h_j exp(+2 pi i (f0 + k df) t_j), k < nf,
+ * as mils_trig_sums but evaluated term by term in FP64 (no time shift).
+ * out_re_im: 2*nf doubles (device).  Synchronous. */
+int mils_direct_trig_sums(mils_context *ctx, const double *t, const double *h, int64_t nd,
+                          double f0, double df, int64_t nf, double *out_re_im,
+                          void *hip_stream);
+
+/*
  * Periodograms of nseries series observed at the same times (the batched
  * mode for series sharing their observation times, Sec. 3.1 of the paper).
  * t: nd doubles; y: nseries x nd doubles, series i at y + i*nd; power:

@@ -530,6 +530,73 @@ int mils_periodogram(mils_context* ctx, const double* t, const double* y, const 
                     reinterpret_cast<hipStream_t>(hip_stream), true);
 }
 
+// Direct evaluation: statistics and the term-by-term sums; the workspace
+// holds only the statistics block and its per-block partials.
+static int run_direct(mils_context* ctx, const double* t, const double* y, const double* dy,
+                      const double* h, int64_t nd, const mils_params* p, double* power,
+                      double* sums, hipStream_t stream) {
+  if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
+  const size_t sb = (sizeof(DevStats) + 255) & ~(size_t)255;
+  int rc = ensure_workspace(ctx, sb + sizeof(double) * 8 * kStatsBlocks);
+  if (rc != MILS_OK) return rc;
+  Work w{};
+  w.stats = reinterpret_cast<DevStats*>(ctx->ws);
+  w.partials = reinterpret_cast<double*>(ctx->ws + sb);
+  CallArgs a{};
+  a.t = t;
+  a.y = y;
+  a.dy = dy;
+  a.h = h;
+  a.nd = nd;
+  a.nf = p->nf;
+  a.f0 = p->f0;
+  a.df = p->df;
+  a.kzero = zero_index(p->f0, p->df, p->nf);
+  a.norm = p->normalization;
+  a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
+  a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.periodogram = y ? 1 : 0;
+  a.power = power;
+  a.sums = sums;
+  he = launch_direct(a, w, stream);
+  if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+  ctx->last_stats = w.stats;
+  ctx->last_stream = stream;
+  ctx->have_pending = true;
+  return mils_context_status(ctx);
+}
+
+int mils_direct_periodogram(mils_context* ctx, const double* t, const double* y,
+                            const double* dy, int64_t nd, const mils_params* p, double* power,
+                            void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  int rc = mils_check_periodogram_args(t, y, nd, p, power);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
+  return run_direct(ctx, t, y, dy, nullptr, nd, p, power, nullptr,
+                    reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+int mils_direct_trig_sums(mils_context* ctx, const double* t, const double* h, int64_t nd,
+                          double f0, double df, int64_t nf, double* out_re_im,
+                          void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  if (!t || !h || !out_re_im) return fail(ctx, MILS_ERR_INVALID_ARG, "null pointer");
+  mils_params p{};
+  p.f0 = f0;
+  p.df = df;
+  p.nf = nf;
+  p.eps = 1e-9;
+  p.precision = MILS_FP64;
+  int rc = check_nd(nd);
+  if (rc == MILS_OK) rc = check_params(&p);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid trig-sum arguments");
+  return run_direct(ctx, t, nullptr, nullptr, h, nd, &p, nullptr, out_re_im,
+                    reinterpret_cast<hipStream_t>(hip_stream));
+}
+
 int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* y,
                               const double* dy, int64_t dy_stride, int64_t nd, int64_t nseries,
                               const mils_params* p, double* power, int32_t* status_per_series,

@@ -14,8 +14,13 @@ __device__ __forceinline__ void dd_two_sum(double a, double b, double& s, double
   e = (a - (s - bb)) + (b - bb);
 }
 
+// The rounded product passes through an empty asm statement: the compiler
+// then cannot contract it into a later subtraction (p - floor(p) would
+// become fma(a, b, -floor(p)), and adding e would count the product's
+// rounding error twice).
 __device__ __forceinline__ void dd_two_prod(double a, double b, double& p, double& e) {
   p = a * b;
+  asm("" : "+v"(p));
   e = __builtin_fma(a, b, -p);
 }
 

@@ -62,6 +62,11 @@ struct SeriesGroup {
 hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
                                const SeriesGroup& sg, hipStream_t s);
 
+// Direct sums at every frequency, term by term, FP64 (statistics into
+// w.stats, which with w.partials is all of w it uses): the power (a.power) or,
+// with a.periodogram == 0, the raw sums of a.h (a.sums, interleaved re/im).
+hipError_t launch_direct(const CallArgs& a, const Work& w, hipStream_t s);
+
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
                          const double* gphi, int q, hipStream_t s);
 

@@ -483,6 +483,124 @@ __global__ __launch_bounds__(kThreads) void k_phihat(double* inv_phihat, int64_t
 }
 
 // ============================================================================
+// Direct sums: the three sums of every frequency evaluated term by term
+// (Sec. 1, Eq. 1), O(N_d N_f), FP64 throughout; a check of the transform at
+// any size and the paper's brute-force comparison.  A thread takes kDirF
+// consecutive frequencies, a workgroup kDirThreads * kDirF; the points stream
+// through LDS in chunks of kDirThreads, each staged once per workgroup:
+// w^ y~, w^, the phase at the workgroup's first frequency fb and the phase
+// step d = df (t - tau) (double-double, reduced mod 1), and exp(2 pi i d).  A
+// thread's first phase is r_b + m d (m = its frequency offset, the product
+// split exactly), reduced and turned into exp(2 pi i .) by sincospi; the
+// next kDirF - 1 follow by multiplication with the step, and B2 uses the
+// square of each.
+// ============================================================================
+constexpr int kDirF = 12;
+constexpr int kDirThreads = 256;
+struct DirPoint {
+  double wy, wh, rb, dh, dl, sc, ss;
+};
+
+__global__ __launch_bounds__(kDirThreads) void k_direct(CallArgs a, Work w) {
+  __shared__ DirPoint pts[kDirThreads];
+  const DevStats st = *w.stats;
+  if (st.status != 0) return;
+  const int tid = threadIdx.x;
+  const int64_t kb = (int64_t)blockIdx.x * kDirThreads * kDirF;
+  const int m = tid * kDirF;
+  const int64_t k0 = kb + m;
+  // fb = f0 + kb df as a double-double
+  double pp, pe;
+  dd_two_prod((double)kb, a.df, pp, pe);
+  double fbh, fbe;
+  dd_two_sum(a.f0, pp, fbh, fbe);
+  const double fbl = fbe + pe;
+  const double invW = 1.0 / st.W;
+  double acc[6][kDirF];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int i = 0; i < kDirF; ++i) acc[q][i] = 0.0;
+  for (int64_t j0 = 0; j0 < a.nd; j0 += kDirThreads) {
+    const int64_t j = j0 + tid;
+    if (j < a.nd) {
+      DirPoint P;
+      const double t = a.t[j];
+      double wj = 1.0;
+      if (a.dy) {
+        const double dv = a.dy[j];
+        wj = 1.0 / (dv * dv);
+      }
+      P.wh = wj * invW;
+      P.wy = a.periodogram ? P.wh * (a.y[j] - st.ysub) : a.h[j];
+      if (!a.periodogram) P.wh = 0.0;
+      double th, tl;
+      dd_two_sum(t, -st.tau, th, tl);
+      // r_b = frac(fb (t - tau))
+      double ah, al;
+      dd_two_prod(fbh, th, ah, al);
+      al = __builtin_fma(fbh, tl, al);
+      al = __builtin_fma(fbl, th, al);
+      double r = (ah - floor(ah)) + al;
+      P.rb = r - rint(r);
+      // d = frac(df (t - tau)) as a double-double
+      double dh, dl;
+      dd_two_prod(a.df, th, dh, dl);
+      dl = __builtin_fma(a.df, tl, dl);
+      const double df0 = dh - floor(dh);
+      double d2h, d2l;
+      dd_two_sum(df0, dl, d2h, d2l);
+      P.dh = d2h;
+      P.dl = d2l;
+      sincospi(2.0 * (d2h + d2l), &P.ss, &P.sc);
+      pts[tid] = P;
+    }
+    __syncthreads();
+    const int cnt = (int)(a.nd - j0 < kDirThreads ? a.nd - j0 : kDirThreads);
+    for (int i = 0; i < cnt; ++i) {
+      const DirPoint P = pts[i];
+      // phase of frequency k0: r_b + m d (mod 1)
+      double mp, me;
+      dd_two_prod((double)m, P.dh, mp, me);
+      double ph = (mp - floor(mp)) + P.rb;
+      ph += __builtin_fma((double)m, P.dl, me);
+      ph -= rint(ph);
+      double zs, zc;
+      sincospi(2.0 * ph, &zs, &zc);
+#pragma unroll
+      for (int f = 0; f < kDirF; ++f) {
+        acc[0][f] = __builtin_fma(P.wy, zc, acc[0][f]);
+        acc[1][f] = __builtin_fma(P.wy, zs, acc[1][f]);
+        acc[2][f] = __builtin_fma(P.wh, zc, acc[2][f]);
+        acc[3][f] = __builtin_fma(P.wh, zs, acc[3][f]);
+        const double c2 = __builtin_fma(zc, zc, -zs * zs);
+        const double s2 = 2.0 * zc * zs;
+        acc[4][f] = __builtin_fma(P.wh, c2, acc[4][f]);
+        acc[5][f] = __builtin_fma(P.wh, s2, acc[5][f]);
+        const double nc = __builtin_fma(zc, P.sc, -zs * P.ss);
+        zs = __builtin_fma(zc, P.ss, zs * P.sc);
+        zc = nc;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int f = 0; f < kDirF; ++f) {
+    const int64_t k = k0 + f;
+    if (k >= a.nf) break;
+    if (a.periodogram) {
+      double pw = ls_power(acc[0][f], acc[1][f], acc[2][f], acc[3][f], acc[4][f], acc[5][f], st,
+                           a.norm, a.fit_mean);
+      if (k == a.kzero) pw = 0.0;
+      a.power[k] = pw;
+    } else {
+      a.sums[2 * k] = acc[0][f];
+      a.sums[2 * k + 1] = acc[1][f];
+    }
+  }
+}
+
+// ============================================================================
 // Host launchers
 // ============================================================================
 static inline unsigned grid_for(int64_t work, int64_t cap) {
@@ -850,6 +968,14 @@ hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
   if (sg.m < 1 || sg.m > 3) return hipErrorInvalidValue;
   if (p.prec == 1) return launch_series_group_t<float>(a, p, w, sg, s);
   return launch_series_group_t<double>(a, p, w, sg, s);
+}
+
+hipError_t launch_direct(const CallArgs& a, const Work& w, hipStream_t s) {
+  enqueue_stats(a, w, s);
+  const int64_t per = (int64_t)kDirThreads * kDirF;
+  const int64_t nb = (a.nf + per - 1) / per;
+  hipLaunchKernelGGL(k_direct, dim3((unsigned)nb), dim3(kDirThreads), 0, s, a, w);
+  return hipGetLastError();
 }
 
 }  // namespace mils

@@ -111,6 +111,10 @@ SIGNATURES = {
     "mils_periodogram_batch": ([_P, ctypes.c_int64, _I64P, _P, _P, _P, _I64P, _D, _D,
                                 ctypes.POINTER(mils_params), _P,
                                 ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
+    "mils_direct_periodogram": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params),
+                                 _P, _P], ctypes.c_int),
+    "mils_direct_trig_sums": ([_P, _P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int64, _P, _P], ctypes.c_int),
     "mils_periodogram_shared_t": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.c_int64,
                                    ctypes.c_int64, ctypes.POINTER(mils_params), _P,
                                    ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
@@ -355,6 +359,43 @@ def periodogram_batch(t, y, dy, nd_off, nf_off, f0, df, eps=1e-9, precision="fp6
     if rc not in (MILS_OK, MILS_ERR_INVALID_ARG, MILS_ERR_DEGENERATE) or not return_status:
         ctx.check(rc)
     return (out, st) if return_status else out
+
+
+def direct_periodogram(t, y, dy, f0, df, nf, normalization="standard", center_data=True,
+                       fit_mean=True, out=None, stream=None, ctx=None):
+    """The periodogram by direct FP64 summation over the points at every
+    frequency (float64 device tensor of nf values)."""
+    import torch
+    t = _dev_f64(t, "t")
+    y = _dev_f64(y, "y")
+    if dy is not None:
+        dy = _dev_f64(dy, "dy")
+    if out is None:
+        out = torch.empty(int(nf), dtype=torch.float64, device=t.device)
+    ctx = ctx or default_context(t.device.index)
+    p = make_params(f0, df, nf, 1e-9, "fp64", normalization, center_data, fit_mean)
+    rc = load().mils_direct_periodogram(
+        ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+        ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, int(t.numel()),
+        ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    ctx.check(rc)
+    return out
+
+
+def direct_trig_sums(t, h, f0, df, nf, stream=None, ctx=None):
+    """sum_j h_j exp(+2 pi i (f0 + k df) t_j), k < nf, by direct FP64 summation
+    (complex128 device tensor)."""
+    import torch
+    t = _dev_f64(t, "t")
+    h = _dev_f64(h, "h")
+    out = torch.empty(2 * int(nf), dtype=torch.float64, device=t.device)
+    ctx = ctx or default_context(t.device.index)
+    rc = load().mils_direct_trig_sums(ctx.handle, ctypes.c_void_p(t.data_ptr()),
+                                      ctypes.c_void_p(h.data_ptr()), int(t.numel()), float(f0),
+                                      float(df), int(nf), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_ptr(stream))
+    ctx.check(rc)
+    return torch.view_as_complex(out.view(-1, 2))
 
 
 def periodogram_shared_t(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64",
