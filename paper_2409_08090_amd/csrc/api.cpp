@@ -841,7 +841,8 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
       const Plan& q = plans[cls_of[c]];
       const int lc = (int)(c - chunk_begin[k]);
-      for (int64_t tl = 0; tl < q.n / q.T; ++tl) ci[k].spread.push_back({lc, (int)tl});
+      const int64_t ntl = (q.n + q.T - 1) / q.T;
+      for (int64_t tl = 0; tl < ntl; ++tl) ci[k].spread.push_back({lc, (int)tl});
       for (int ip = 0; ip + 1 < q.npass; ++ip) {
         const FftPass& ps = q.pass[ip];
         const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);

@@ -266,8 +266,15 @@ __global__ __launch_bounds__(NT) void k_bspread(BatchArgs ba, const BatchItem* i
   const BatchCurve c = ba.curves[it.curve];
   const Work& w = ba.works[it.curve];
   const Plan* pl = ba.plans + c.plan;
-  const int row = (int)(((int64_t)it.sub * pl->T) / pl->S1);
-  if ((GEO == 1 ? w.rowflag_f : w.rowflag_2f)[row] == 0) return;
+  // a tile is one row or part of one, or (short rows) several whole rows
+  const int64_t a0 = (int64_t)it.sub * pl->T;
+  const int64_t r0 = a0 / pl->S1;
+  int64_t r1 = (a0 + pl->T - 1) / pl->S1;
+  if (r1 >= pl->nrows) r1 = pl->nrows - 1;
+  const unsigned char* flags = GEO == 1 ? w.rowflag_f : w.rowflag_2f;
+  int any = 0;
+  for (int64_t r = r0; r <= r1; ++r) any |= flags[r];
+  if (!any) return;
   const DevStats st = *w.stats;
   if (st.status != 0) return;
   load_plan(pl, &sp);

@@ -373,11 +373,20 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   }
   int T = 1;
   const int tmax = r.tile_max > 0 ? std::min(r.tile_max, kTileMaxCells) : kTileMaxCells;
-  for (int d = (int)std::min<int64_t>(p.S1, tmax); d >= 1; --d)
-    if (p.S1 % d == 0) {
-      T = d;
-      break;
-    }
+  if (r.batch && r.tile_max > 0 && p.nrows > 1 && 2 * p.S1 <= tmax) {
+    // batched series with an explicit tile cap (the batch autotuner's
+    // candidates): a tile of several whole rows (the last one may be
+    // shorter), so that short rows do not make many nearly empty tiles when
+    // there are many series; without a cap a lone series keeps more, smaller
+    // tiles
+    T = (int)((tmax / p.S1) * p.S1);
+  } else {
+    for (int d = (int)std::min<int64_t>(p.S1, tmax); d >= 1; --d)
+      if (p.S1 % d == 0) {
+        T = d;
+        break;
+      }
+  }
   p.T = T;
   p.Tb = best_n >= 4096 ? 32 : 8;
   p.Tb_shift = best_n >= 4096 ? 5 : 3;
