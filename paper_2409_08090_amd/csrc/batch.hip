@@ -96,7 +96,6 @@ __device__ void stats_block(const CallArgs& a, DevStats* st, double* sh /* 5*NT 
     st->nlow = 0;
     st->k_lo = 0;
   }
-  __threadfence();
   __syncthreads();
 }
 
@@ -129,15 +128,12 @@ __device__ void bins_block(const CallArgs& a, const Plan& p, const Work& w, DevS
     }
     if (desc) atomicOr(&flag[0], 1);
   }
-  __threadfence();
   __syncthreads();
   if (!flag[0]) return;
   // counting sort
   for (int b = tid; b <= nb; b += NT) w.bin_count[b] = 0;
-  __threadfence();
   __syncthreads();
   for (int j = tid; j < nd; j += NT) atomicAdd(&w.bin_count[point_bin(a.t[j], tau, a.df, p)], 1);
-  __threadfence();
   __syncthreads();
   // exclusive scan of bin_count[0..nb] in chunks of NT
   int carry = 0;
@@ -160,7 +156,6 @@ __device__ void bins_block(const CallArgs& a, const Plan& p, const Work& w, DevS
     carry += shi[NT - 1];
     __syncthreads();
   }
-  __threadfence();
   __syncthreads();
   for (int j = tid; j < nd; j += NT) {
     const double t = a.t[j];
@@ -171,7 +166,6 @@ __device__ void bins_block(const CallArgs& a, const Plan& p, const Work& w, DevS
     w.dys[pos] = a.dy ? a.dy[j] : 1.0;
   }
   if (tid == 0) st->need_sort = 1;
-  __threadfence();
   __syncthreads();
 }
 
@@ -192,7 +186,6 @@ __device__ void lowfreq_block(const CallArgs& a, DevStats* st, double* lowfix, d
     st->k_lo = k_lo;
     st->nlow = nlow;
   }
-  __threadfence();
   __syncthreads();
 }
 
