@@ -315,7 +315,8 @@ struct PassBufs {
 // transforms along L in LDS, applies the inter-pass twiddle and stores with
 // the outer index and k transposed.  One workgroup's share of the pass is the
 // logical block blk.  smem: L*C elements + the twiddle table (L entries, or
-// tw2_count(L) for TW2) + L row flags.  C is a power of two that divides NT,
+// tw2_count(L) for TW2) + L row flags; rflag (NULL: every row) marks the
+// input rows that are not all zero.  C is a power of two that divides NT,
 // so a thread keeps one column c = tid mod C and visits rows l0, l0 + NT/C,
 // ... (l0 = tid / C): its global addresses are a base plus uniform strides.
 template <typename Real, int EMAX, int NT, bool TW2 = false>
@@ -329,29 +330,43 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
   const int ntw = TW2 ? tw2_count(L) : L;
   T2* buf = reinterpret_cast<T2*>(smem);
   T2* twL = buf + L * C;
-  unsigned char* rf = reinterpret_cast<unsigned char*>(twL + ntw);
   const int64_t S = ps.S, P = ps.P;
   const uint32_t nsb = (uint32_t)((S + C - 1) / C);
   const uint32_t pidx32 = (uint32_t)blk / nsb;
   const int64_t pidx = pidx32;
   const int64_t s0 = (int64_t)((uint32_t)blk - pidx32 * nsb) * C;
   const int ceff = (int)((S - s0) < C ? (S - s0) : C);
-  for (int x = tid; x < ntw; x += NT) twL[x] = tw[ps.twL_off + x];
-  for (int x = tid; x < L; x += NT) rf[x] = rflag ? rflag[x] : (unsigned char)1;
   const int c = tid & (C - 1);
   const int l0 = tid >> csh;
   const int LS = NT >> csh;  // rows between a thread's consecutive elements
   const bool cok = c < ceff;
-  __syncthreads();
   constexpr int PER = (EMAX + NT - 1) / NT;
   const T2* pin = in + pidx * (int64_t)L * S + s0 + (int64_t)l0 * S + c;
   const int64_t istep = (int64_t)LS * S;
   T2 v[PER];
+  if (rflag) {
+    // first pass: the row flags (and the twiddle table) into LDS, then the
+    // loads of the rows that are not all zero
+    unsigned char* rf = reinterpret_cast<unsigned char*>(twL + ntw);
+    for (int x = tid; x < ntw; x += NT) twL[x] = tw[ps.twL_off + x];
+    for (int x = tid; x < L; x += NT) rf[x] = rflag[x];
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int l = l0 + i * LS;
-    v[i] = czero<T2>();
-    if (l < L && cok && rf[l]) v[i] = pin[i * istep];
+    for (int i = 0; i < PER; ++i) {
+      const int l = l0 + i * LS;
+      v[i] = czero<T2>();
+      if (l < L && cok && rf[l]) v[i] = pin[i * istep];
+    }
+  } else {
+    // later passes: the tile's loads first, then the twiddle table, whose
+    // loads and LDS stores overlap the data's latency
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int l = l0 + i * LS;
+      v[i] = czero<T2>();
+      if (l < L && cok) v[i] = pin[i * istep];
+    }
+    for (int x = tid; x < ntw; x += NT) twL[x] = tw[ps.twL_off + x];
   }
 #pragma unroll
   for (int i = 0; i < PER; ++i)
