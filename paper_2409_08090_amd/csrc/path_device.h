@@ -462,7 +462,6 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
   const int64_t P = ps.P;
   const int64_t p0 = blk * D;
   const int deff = (int)((P - p0) < D ? (P - p0) : D);
-  for (int x = tid; x < (TW2 ? tw2_count(L) : L); x += NT) twL[x] = tw[ps.twL_off + x];
   const int E = D * L;
   const int dsh = __builtin_ctz(D);  // D is a power of two
   constexpr int PER = (EMAX / G + NT - 1) / NT;
@@ -470,21 +469,26 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
   const int d0 = tid & (D - 1);
   const int l0 = tid >> dsh;
   const int LS = NT >> dsh;  // NT is a multiple of D
+  // the rows' loads first, then the twiddle table (its latency hides behind
+  // theirs), then the rows into LDS
+  T2 v[G][PER];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const T2* in = b.in[g] + (p0 + d0) * (int64_t)L + l0;
-    T2 v[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      v[i] = czero<T2>();
-      if (l0 + i * LS < L && d0 < deff) v[i] = in[i * LS];
+      v[g][i] = czero<T2>();
+      if (l0 + i * LS < L && d0 < deff) v[g][i] = in[i * LS];
     }
+  }
+  for (int x = tid; x < (TW2 ? tw2_count(L) : L); x += NT) twL[x] = tw[ps.twL_off + x];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int l = l0 + i * LS;
-      if (l < L) buf[__mul24(l, R) + g * D + d0] = v[i];
+      if (l < L) buf[__mul24(l, R) + g * D + d0] = v[g][i];
     }
-  }
   __syncthreads();
   // kernel-transform factors of this thread's outputs, fetched before the
   // transform so that their latency overlaps it (-1: output cropped)
