@@ -212,3 +212,32 @@ def test_single_large_full_size_sampled(precision):
           f"{err:.3e}", flush=True)
     assert err <= TOL[precision]
     assert np.all(np.isfinite(p)) and p.min() >= -1e-6 and p.max() <= 1 + 1e-6
+
+
+# ---------------------------------------------------------------- library special case
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trig_sums_on_a_uniform_grid_are_a_dft(precision):
+    """With t_j = j / N and f_k = k the raw sums are sum_j h_j exp(2 pi i j k / N),
+    N times numpy's inverse DFT (a library routine, pocketfft)."""
+    N = 4096
+    rng = np.random.default_rng(41)
+    t = np.arange(N) / N
+    h = rng.normal(0.0, 1.0, N)
+    nf = 1500
+    eps = {"fp64": 1e-9, "fp32": 1e-5}[precision]
+    g = mils.trig_sums(dev(t), dev(h), 0.0, 1.0, nf, eps=eps, precision=precision)
+    g = g.cpu().numpy()
+    ref = N * np.fft.ifft(h)[:nf]
+    err = np.max(np.abs(g - ref))
+    print(f"[uniform-grid sums {precision}] max error {err:.3e} = "
+          f"{err / np.sum(np.abs(h)):.3e} sum|h|", flush=True)
+    assert err <= 10 * eps * np.sum(np.abs(h))
+
+
+def test_repeated_calls_agree():
+    """The spread accumulates in LDS with atomic adds, whose order may differ
+    from run to run; results then differ only by rounding."""
+    c = workloads.single_large(seed=1, nd=200_000, span_years=4)
+    runs = [gpu_power(c) for _ in range(3)]
+    for r in runs[1:]:
+        assert np.max(np.abs(r - runs[0])) <= 1e-13 * np.max(np.abs(runs[0]))
