@@ -71,7 +71,14 @@ enum { MILS_NORM_STANDARD = 0, MILS_NORM_MODEL = 1, MILS_NORM_LOG = 2, MILS_NORM
 /* Flags. */
 enum {
   MILS_CENTER_DATA = 1, /* subtract the weighted mean of y before the sums */
-  MILS_FIT_MEAN = 2     /* include a constant offset in the fitted model ("floating mean") */
+  MILS_FIT_MEAN = 2,    /* include a constant offset in the fitted model ("floating mean") */
+  /* Bitwise-reproducible results (mils_periodogram, mils_periodogram_async):
+   * every sum is accumulated in a fixed order -- the points are binned by a
+   * sort on (bin, index) instead of the counting sort, and the spread adds
+   * them to each grid cell in that order instead of with atomic adds.  Slower
+   * (about 3x at N_d = 1e6); other calls reject it with MILS_ERR_UNSUPPORTED.
+   * Without it, repeated calls agree to rounding. */
+  MILS_DETERMINISTIC = 4
 };
 
 typedef struct mils_context mils_context;
@@ -85,7 +92,7 @@ typedef struct {
   double eps;            /* requested NUFFT tolerance: FP64 [1e-14, 1e-2], FP32 [1e-6, 1e-2] */
   int32_t precision;     /* MILS_FP64 or MILS_FP32 */
   int32_t normalization; /* MILS_NORM_* */
-  uint32_t flags;        /* MILS_CENTER_DATA | MILS_FIT_MEAN (the default) */
+  uint32_t flags;        /* MILS_CENTER_DATA | MILS_FIT_MEAN (the default), MILS_DETERMINISTIC */
 } mils_params;
 
 /* What the planner chose for a problem (host-only query). */

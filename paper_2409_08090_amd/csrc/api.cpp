@@ -162,7 +162,8 @@ int check_params(const mils_params* p) {
   if (p->nf > ((int64_t)1 << 28)) return MILS_ERR_UNSUPPORTED;
   if (p->precision != MILS_FP64 && p->precision != MILS_FP32) return MILS_ERR_INVALID_ARG;
   if (p->normalization < 0 || p->normalization > 3) return MILS_ERR_INVALID_ARG;
-  if (p->flags & ~(uint32_t)(MILS_CENTER_DATA | MILS_FIT_MEAN)) return MILS_ERR_INVALID_ARG;
+  if (p->flags & ~(uint32_t)(MILS_CENTER_DATA | MILS_FIT_MEAN | MILS_DETERMINISTIC))
+    return MILS_ERR_INVALID_ARG;
   if (!std::isfinite(p->eps) || !(p->eps > 0.0)) return MILS_ERR_INVALID_ARG;
   const double lo = p->precision == MILS_FP64 ? 1e-14 : 1e-6;
   if (p->eps < lo || p->eps > 1e-2) return MILS_ERR_UNSUPPORTED;
@@ -335,6 +336,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
   a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
   a.periodogram = pg ? 1 : 0;
+  a.deterministic = (p->flags & MILS_DETERMINISTIC) ? 1 : 0;
   a.power = power;
   a.sums = sums;
   StageHook hook{prof_hook, ctx};
@@ -608,6 +610,8 @@ int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* 
     return fail(ctx, MILS_ERR_INVALID_ARG, "nseries must be in [1, 2^24]");
   if (dy && dy_stride != 0 && dy_stride != nd)
     return fail(ctx, MILS_ERR_INVALID_ARG, "dy_stride must be 0 (shared dy) or nd");
+  if (p->flags & MILS_DETERMINISTIC)
+    return fail(ctx, MILS_ERR_UNSUPPORTED, "MILS_DETERMINISTIC applies to single-series calls");
   if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
   if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
   hipError_t he = hipSetDevice(ctx->device);
@@ -1083,6 +1087,8 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
       !common || !t || !y || !power)
     return fail(ctx, MILS_ERR_INVALID_ARG, "invalid batch arguments");
   if (nd_off[0] != 0 || nf_off[0] != 0) return fail(ctx, MILS_ERR_INVALID_ARG, "offsets must start at 0");
+  if (common->flags & MILS_DETERMINISTIC)
+    return fail(ctx, MILS_ERR_UNSUPPORTED, "MILS_DETERMINISTIC applies to single-series calls");
   for (int64_t c = 0; c < ncurves; ++c) {
     mils_params p = *common;
     p.f0 = f0[c];

@@ -270,6 +270,75 @@ __global__ __launch_bounds__(kThreads) void k_sort_scatter(CallArgs a, Plan p, W
 }
 
 // ============================================================================
+// Reproducible binning (deterministic calls): the points in the order of the
+// keys bin << 32 | index, sorted by a bitonic network (the keys are distinct,
+// so the order is unique), gathered into the sorted copies; bin_start by a
+// binary search per bin.  Replaces the counting sort, whose order within a
+// bin follows atomic arrivals.
+// ============================================================================
+__global__ __launch_bounds__(kThreads) void k_det_keys(CallArgs a, Plan p, Work w, int64_t nk) {
+  const DevStats* st = w.stats;
+  if (st->status != 0) return;
+  const double tau = st->tau;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nk;
+       i += (int64_t)gridDim.x * kThreads) {
+    uint64_t key = ~(uint64_t)0;
+    if (i < a.nd) key = ((uint64_t)(uint32_t)point_bin(a.t[i], tau, a.df, p) << 32) | (uint64_t)i;
+    w.keys[i] = key;
+  }
+}
+
+// One compare-exchange step (block size k, distance jj) of the ascending
+// bitonic sort of nk keys (nk a power of two): each pair (i, i ^ jj) is taken
+// by the thread of its lower index.
+__global__ __launch_bounds__(kThreads) void k_det_bitonic(Work w, int64_t nk, int64_t k, int64_t jj) {
+  if (w.stats->status != 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nk;
+       i += (int64_t)gridDim.x * kThreads) {
+    const int64_t l = i ^ jj;
+    if (l <= i) continue;
+    const uint64_t x = w.keys[i], y = w.keys[l];
+    const bool up = (i & k) == 0;
+    if ((x > y) == up) {
+      w.keys[i] = y;
+      w.keys[l] = x;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_det_gather(CallArgs a, Plan p, Work w) {
+  DevStats* st = w.stats;
+  if (st->status != 0) return;
+  const int nd = (int)a.nd;
+  const int nb = (int)p.nbins;
+  const int64_t total = nd > nb + 1 ? nd : nb + 1;
+  for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * kThreads) {
+    if (q < nd) {
+      const int j = (int)(w.keys[q] & 0xffffffffu);
+      w.ts[q] = a.t[j];
+      if (a.periodogram) {
+        w.ys[q] = a.y ? a.y[j] : 0.0;
+        w.dys[q] = a.dy ? a.dy[j] : 1.0;
+      } else {
+        w.hs[q] = a.h[j];
+      }
+    }
+    if (q <= nb) {
+      // first position whose bin is >= q (nd if none)
+      int lo = 0, hi = nd;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)(w.keys[mid] >> 32) < (int)q) lo = mid + 1;
+        else hi = mid;
+      }
+      w.bin_start[q] = lo;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->need_sort = 1;  // the spread reads the copies
+}
+
+// ============================================================================
 // Spreading.  A tile is T consecutive cells of one row of the [nrows][S1]
 // view of the grid; its workgroup gathers every point whose kernel support
 // (w cells around u) meets the tile, accumulates the kernel-weighted
@@ -323,7 +392,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int n
 // from k_row_class): a fixed grid of workgroups takes tiles blk, blk + grid,
 // ...; every tile is written by exactly one workgroup, so the result does not
 // depend on scheduling.  T divides the row length S1 here.
-template <typename Real, int GEO, int NG>
+template <typename Real, int GEO, int NG, bool DET = false>
 __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Work w, int gbase,
                                                           const int* act_rows, int slot) {
   __shared__ Real acc[NG * 2 * kTileMax];
@@ -336,8 +405,8 @@ __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Wo
   for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
     const int q = t / tpr;
     const int tile = act_rows[q] * tpr + (t - q * tpr);
-    spread_tile<Real, GEO, NG, kThreads, true>(tile, p.T, kTileMax, a, p, w, *stp, gbase, nullptr,
-                                               acc, rb, re, sv, rec);
+    spread_tile<Real, GEO, NG, kThreads, true, DET>(tile, p.T, kTileMax, a, p, w, *stp, gbase,
+                                                    nullptr, acc, rb, re, sv, rec);
   }
 }
 
@@ -643,6 +712,18 @@ static void enqueue_bins(const CallArgs& a, const Plan& p, const Work& w, hipStr
   hipLaunchKernelGGL(k_sort_scatter, dim3(sort_blocks), dim3(kThreads), 0, s, a, p, w);
 }
 
+// Reproducible binning (see k_det_keys).
+static void enqueue_det_bins(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s) {
+  const int64_t nk = det_keys(a.nd);
+  const unsigned g = grid_for(nk, 1 << 16);
+  hipLaunchKernelGGL(k_det_keys, dim3(g), dim3(kThreads), 0, s, a, p, w, nk);
+  for (int64_t k = 2; k <= nk; k <<= 1)
+    for (int64_t jj = k >> 1; jj > 0; jj >>= 1)
+      hipLaunchKernelGGL(k_det_bitonic, dim3(g), dim3(kThreads), 0, s, w, nk, k, jj);
+  const int64_t nbt = (a.nd > p.nbins + 1 ? a.nd : p.nbins + 1);
+  hipLaunchKernelGGL(k_det_gather, dim3(grid_for(nbt, 1 << 16)), dim3(kThreads), 0, s, a, p, w);
+}
+
 // Direct sums near f = 0 into w.lowfix.
 static void enqueue_lowfreq(const CallArgs& a, const Work& w, hipStream_t s) {
   const unsigned lb = grid_for(a.nd, kLowBlocks);
@@ -779,7 +860,8 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   enqueue_stats(a, w, s);
   mark(kStageStats, 0, s);
   mark(kStageBin, 1, s);
-  enqueue_bins(a, p, w, s);
+  if (a.deterministic) enqueue_det_bins(a, p, w, s);
+  else enqueue_bins(a, p, w, s);
   mark(kStageBin, 0, s);
   if (fork) {
     hipError_t e = hipEventRecord(aux->fork, s);
@@ -799,14 +881,21 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     mark(kStageSpread2F, 1, s2);
     hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd, w.rowflag_2f,
                        w.act_rows_2f, 1);
-    hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w, 2,
-                       w.act_rows_2f, 1);
+    if (a.deterministic)
+      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1, true>), dim3(sgrid), dim3(kThreads), 0, s2, a,
+                         p, w, 2, w.act_rows_2f, 1);
+    else
+      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w,
+                         2, w.act_rows_2f, 1);
     mark(kStageSpread2F, 0, s2);
   }
   mark(kStageSpreadF, 1, s);
   hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
                      w.act_rows_f, 0);
-  if (a.periodogram)
+  if (a.periodogram && a.deterministic)
+    hipLaunchKernelGGL((k_spread_rows<Real, 1, 2, true>), dim3(sgrid), dim3(kThreads), 0, s, a, p,
+                       w, 0, w.act_rows_f, 0);
+  else if (a.periodogram)
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 2>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
                        w.act_rows_f, 0);
   else

@@ -94,6 +94,7 @@ struct CallArgs {
   int norm;
   int center, fit_mean;
   int periodogram;    // 1: three grids + power; 0: one grid + complex sums
+  int deterministic;  // fixed summation orders (bitwise-reproducible results)
   double* power;      // periodogram output
   double* sums;       // trig sums output (interleaved re/im)
   // Series sharing their weights (same t and dy): a weights-only call has
@@ -139,7 +140,15 @@ struct Work {
   const double* inv_phihat;  // 1 / phihat(|m|), m = 0..K (plan-owned)
   double* lowpart;        // per-block partial direct sums near f = 0
   double* lowfix;         // direct sums A, B, B2 near f = 0: kLowParts rows of kLowMax x 6
+  uint64_t* keys;         // det_keys(nd) sort keys of the reproducible binning
 };
+
+// Keys of the reproducible binning: the next power of two >= nd (>= 2).
+inline int64_t det_keys(int64_t nd) {
+  int64_t k = 2;
+  while (k < nd) k <<= 1;
+  return k;
+}
 
 constexpr int kStatsBlocks = 1024;
 constexpr int kThreads = 256;       // threads of most kernels

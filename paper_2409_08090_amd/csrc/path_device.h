@@ -125,7 +125,7 @@ struct SpreadRecords {
 // tile of inactive rows returns at once.  acc: LDS accumulator of NG*2*tcap
 // Reals (T <= tcap); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by
 // every thread of the workgroup (it contains barriers).
-template <typename Real, int GEO, int NG, int NT, bool KNOWN = false>
+template <typename Real, int GEO, int NG, int NT, bool KNOWN = false, bool DET = false>
 __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const Plan& p,
                             const Work& w, const DevStats& st, int gbase, unsigned char* rowflag,
                             Real* acc, int* rb, int* re, int* sv,
@@ -266,6 +266,29 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
       __syncthreads();
       // (2) the chunk's points, KL lanes each
       const int cnt = jend - base < NT ? jend - base : NT;
+      if constexpr (DET) {
+        // fixed order: each thread owns cells x = tid, tid + NT, ... of the
+        // tile and adds the chunk's points to them one after another (no
+        // atomics; the point order is the binning's, itself fixed)
+        for (int i = 0; i < cnt; ++i) {
+          const int lb = rec.lb[i];
+          if (lb == kSpreadNone) continue;
+          const Real u = rec.u[i];
+          for (int x = tid; x < T; x += NT) {
+            int off = x - lb;  // cell offset within the point's support, mod n
+            if (off < 0) off += n;
+            else if (off >= n) off -= n;
+            if (off >= wd) continue;
+            Real v = hc[off];
+            for (int jc = 1; jc < NC; ++jc) v = v * u + hc[jc * kHornerK + off];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+              acc[(2 * g) * tcap + x] += v * rec.h[(2 * g) * NT + i];
+              acc[(2 * g + 1) * tcap + x] += v * rec.h[(2 * g + 1) * NT + i];
+            }
+          }
+        }
+      } else
       for (int it = 0; it * Q * nwave < NT; ++it) {
         const int i = q * (NT / Q) + wave + nwave * it;  // point slot
         if (i >= cnt) continue;

@@ -491,6 +491,7 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w, bool p
     x.hs = reinterpret_cast<double*>(take(sizeof(double) * nd));
   }
   if (!per_series) x.lowpart = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * kLowBlocks));
+  if (!per_series) x.keys = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * det_keys(nd)));
   x.lowfix = reinterpret_cast<double*>(take(sizeof(double) * 6 * kLowMax * (per_series ? 1 : kLowParts)));
   x.rowflag_f = reinterpret_cast<unsigned char*>(take(p.nrows));
   x.rowflag_2f = reinterpret_cast<unsigned char*>(take(p.nrows));

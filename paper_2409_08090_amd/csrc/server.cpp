@@ -348,6 +348,7 @@ int mils_server_submit(mils_server* srv, const mils_request* req, uint64_t* tick
   if (!srv || !req || !ticket || !req->t || !req->y) return MILS_ERR_INVALID_ARG;
   int rc = mils_check_params(&req->params, req->nd);
   if (rc != MILS_OK) return rc;
+  if (req->params.flags & MILS_DETERMINISTIC) return MILS_ERR_UNSUPPORTED;
   const uint64_t rb = request_bytes(req->params, req->nd);
   auto r = std::make_unique<Request>();
   const size_t nd = (size_t)req->nd;

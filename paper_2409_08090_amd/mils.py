@@ -29,6 +29,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1}
 NORMALIZATIONS = {"standard": 0, "model": 1, "log": 2, "psd": 3}
 MILS_CENTER_DATA = 1
 MILS_FIT_MEAN = 2
+MILS_DETERMINISTIC = 4
 
 
 class mils_params(ctypes.Structure):
@@ -233,8 +234,9 @@ def default_context(device: int | None = None) -> Context:
 
 
 def make_params(f0, df, nf, eps=1e-9, precision="fp64", normalization="standard",
-                center_data=True, fit_mean=True) -> mils_params:
-    flags = (MILS_CENTER_DATA if center_data else 0) | (MILS_FIT_MEAN if fit_mean else 0)
+                center_data=True, fit_mean=True, deterministic=False) -> mils_params:
+    flags = ((MILS_CENTER_DATA if center_data else 0) | (MILS_FIT_MEAN if fit_mean else 0) |
+             (MILS_DETERMINISTIC if deterministic else 0))
     return mils_params(float(f0), float(df), int(nf), float(eps), PRECISIONS[precision],
                        NORMALIZATIONS[normalization], flags)
 
@@ -289,8 +291,10 @@ def _stream_ptr(stream):
 
 
 def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization="standard",
-                center_data=True, fit_mean=True, out=None, stream=None, ctx=None, sync=True):
-    """Lomb-Scargle power at f0 + k df, k < nf (float64 device tensor)."""
+                center_data=True, fit_mean=True, out=None, stream=None, ctx=None, sync=True,
+                deterministic=False):
+    """Lomb-Scargle power at f0 + k df, k < nf (float64 device tensor);
+    deterministic: bitwise-reproducible summation order (slower)."""
     import torch
     t = _dev_f64(t, "t")
     y = _dev_f64(y, "y")
@@ -299,7 +303,8 @@ def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization=
     if out is None:
         out = torch.empty(int(nf), dtype=torch.float64, device=t.device)
     ctx = ctx or default_context(t.device.index)
-    p = make_params(f0, df, nf, eps, precision, normalization, center_data, fit_mean)
+    p = make_params(f0, df, nf, eps, precision, normalization, center_data, fit_mean,
+                    deterministic)
     fn = load().mils_periodogram if sync else load().mils_periodogram_async
     rc = fn(ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
             ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, int(t.numel()),

@@ -57,7 +57,8 @@ def per_dispatch(d, counter):
 
 
 def _is_2f(name):
-    return "Li2ELi1E" in name or "<double, 2, 1>" in name or "<float, 2, 1>" in name
+    """The 2f-geometry spread (template arguments <Real, 2, 1, ...>)."""
+    return "Li2ELi1E" in name or "<double, 2, 1" in name or "<float, 2, 1" in name
 
 
 def stage_bytes(disp, scale):

@@ -79,6 +79,8 @@ def test_argument_validation_codes():
     p = mils.make_params(0.01, 0.01, 100)
     p.flags = 8
     assert _check(P, P, 10, p, P) == mils.MILS_ERR_INVALID_ARG
+    # the reproducible mode is a valid flag
+    assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, deterministic=True), P) == mils.MILS_OK
     # tolerance outside the precision's range, or too many frequencies
     assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, eps=1e-15), P) == mils.MILS_ERR_UNSUPPORTED
     assert _check(P, P, 10, mils.make_params(0.01, 0.01, 100, eps=1e-7, precision="fp32"),

@@ -241,3 +241,55 @@ def test_repeated_calls_agree():
     runs = [gpu_power(c) for _ in range(3)]
     for r in runs[1:]:
         assert np.max(np.abs(r - runs[0])) <= 1e-13 * np.max(np.abs(runs[0]))
+
+
+# ---------------------------------------------------------------- reproducible mode
+@pytest.mark.parametrize("sorted_t", [True, False])
+def test_deterministic_mode_is_bitwise_reproducible(sorted_t):
+    c = workloads.single_large(seed=1, nd=150_000, span_years=4)
+    if not sorted_t:
+        perm = np.random.default_rng(5).permutation(c.nd)
+        c.t, c.y, c.dy = c.t[perm], c.y[perm], c.dy[perm]
+    runs = [gpu_power(c, deterministic=True) for _ in range(3)]
+    for r in runs[1:]:
+        assert np.array_equal(r, runs[0])
+    k = np.unique(np.concatenate([np.arange(40), np.random.default_rng(6).integers(0, c.nf, 150),
+                                  np.argsort(runs[0])[-20:]]))
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+    assert rel_err(runs[0][k], ref) <= 1e-8
+    fast = gpu_power(c)
+    assert np.max(np.abs(fast - runs[0])) <= 1e-12 * np.max(np.abs(runs[0]))
+
+
+def test_deterministic_mode_small_full_grid_and_fp32():
+    c = workloads.single_small(seed=0)
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, nf=c.nf)
+    assert rel_err(gpu_power(c, deterministic=True), ref) <= 1e-8
+    p32 = [gpu_power(c, "fp32", deterministic=True) for _ in range(2)]
+    assert np.array_equal(p32[0], p32[1])
+    assert rel_err(p32[0], ref) <= 1e-4
+
+
+def test_deterministic_flag_rejected_outside_single_series():
+    import ctypes
+    s = workloads.shared_times(seed=59, nd=300, nseries=2, span_years=2)
+    lib = mils.load()
+    ctx = mils.default_context()
+    t, y = dev(s.t), dev(s.y)
+    out = torch.empty((2, s.nf), dtype=torch.float64, device="cuda")
+    prm = mils.make_params(s.f0, s.df, s.nf, deterministic=True)
+    rc = lib.mils_periodogram_shared_t(ctx.handle, ctypes.c_void_p(t.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), None, 0, s.nd, 2,
+                                       ctypes.byref(prm), ctypes.c_void_p(out.data_ptr()), None,
+                                       None)
+    assert rc == mils.MILS_ERR_UNSUPPORTED
+    bt, by, bdy, nd_off, nf_off, f0s, dfs = mils.pack_curves([s.curve(0), s.curve(1)])
+    bout = torch.empty(int(nf_off[-1]), dtype=torch.float64, device="cuda")
+    prm = mils.make_params(0.0, 1.0, 1, deterministic=True)
+    rc = lib.mils_periodogram_batch(
+        ctx.handle, 2, nd_off.ctypes.data_as(mils._I64P), ctypes.c_void_p(bt.data_ptr()),
+        ctypes.c_void_p(by.data_ptr()), ctypes.c_void_p(bdy.data_ptr()),
+        nf_off.ctypes.data_as(mils._I64P), f0s.ctypes.data_as(mils._D),
+        dfs.ctypes.data_as(mils._D), ctypes.byref(prm), ctypes.c_void_p(bout.data_ptr()), None,
+        None)
+    assert rc == mils.MILS_ERR_UNSUPPORTED

@@ -40,6 +40,13 @@ def test_incomplete_periodogram_is_ignored():
     assert abs(got["stats"] - 2.0) < 1e-9
 
 
+def test_spread_names_with_more_template_arguments():
+    step = [(0, n.replace("<double, 2, 1>", "<double, 2, 1, false>")
+             .replace("<double, 1, 2>", "<double, 1, 2, false>"), k) for _, n, k in _step()]
+    got = traffic.stage_bytes(step, 1.0 / 1024.0)
+    assert abs(got["spread_2f"] - 6.0) < 1e-9 and abs(got["fft_pass_0"] - 24.0) < 1e-9
+
+
 def test_copy_scale():
     disp = [(0, "__amd_rocclr_copyBuffer", traffic.COPY_BYTES / 1024.0 / 2.0)]
     assert abs(traffic.copy_scale(disp) - 2.0) < 1e-12
