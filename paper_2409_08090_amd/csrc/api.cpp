@@ -248,10 +248,34 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   return MILS_OK;
 }
 
+// Size for a buffer that must hold `need` bytes and holds `have`: half
+// again as large as before at least, so that growing requests (a server's
+// mix of sizes) reallocate rarely -- a reallocation waits for the device --
+// and within `room` when room > 0.
+size_t grow_to(size_t need, size_t have, size_t room) {
+  size_t s = std::max(need, have + have / 2);
+  if (room && s > room) s = std::max(need, room);
+  return s;
+}
+
+// Device allocation of `want` bytes, or of `need` if that fails.
+hipError_t malloc_grown(char** p, size_t want, size_t need, size_t* got) {
+  if (want > need && hipMalloc(p, want) == hipSuccess) {
+    *got = want;
+    return hipSuccess;
+  }
+  (void)hipGetLastError();
+  hipError_t he = hipMalloc(p, need);
+  *got = he == hipSuccess ? need : 0;
+  return he;
+}
+
 int ensure_workspace(mils_context* ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return MILS_OK;
   if (ctx->budget && ctx->plan_bytes + bytes > ctx->budget)
     return fail(ctx, MILS_ERR_OOM, "workspace exceeds the HBM budget");
+  const size_t room = ctx->budget ? ctx->budget - ctx->plan_bytes : 0;
+  const size_t want = grow_to(bytes, ctx->ws_bytes, room);
   if (ctx->ws) {
     hipError_t he = hipDeviceSynchronize();
     if (he != hipSuccess) return hip_fail(ctx, he, "workspace resize");
@@ -260,12 +284,13 @@ int ensure_workspace(mils_context* ctx, size_t bytes) {
     ctx->ws_bytes = 0;
   }
   char* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
+  size_t got = 0;
+  if (malloc_grown(&p, want, bytes, &got) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, MILS_ERR_OOM, "hipMalloc of the workspace failed");
   }
   ctx->ws = p;
-  ctx->ws_bytes = bytes;
+  ctx->ws_bytes = got;
   // the statistics block holds the self-resetting reduction counter
   hipError_t he = hipMemset(p, 0, 4096);
   if (he != hipSuccess) return hip_fail(ctx, he, "workspace init");
@@ -895,25 +920,30 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
   he = hipStreamSynchronize(stream);
   if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
+  // room left by the budget for the batch's two buffers (0: no budget)
+  const size_t room = ctx->budget ? ctx->budget - ctx->plan_bytes - ctx->ws_bytes : 0;
   if (B.dev_bytes < dev_bytes) {
+    const size_t had = B.dev_bytes;
     if (B.dev) (void)hipFree(B.dev);
     B.dev = nullptr;
     B.dev_bytes = 0;
-    if (hipMalloc(&B.dev, dev_bytes) != hipSuccess) {
+    const size_t want = grow_to(dev_bytes, had, room ? room - ws_max : 0);
+    if (malloc_grown(&B.dev, want, dev_bytes, &B.dev_bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch descriptors failed");
     }
-    B.dev_bytes = dev_bytes;
   }
   if (B.ws_bytes < ws_max) {
+    const size_t had = B.ws_bytes;
     if (B.ws) (void)hipFree(B.ws);
     B.ws = nullptr;
     B.ws_bytes = 0;
-    if (hipMalloc(&B.ws, ws_max) != hipSuccess) {
+    const size_t left = room > B.dev_bytes + ws_max ? room - B.dev_bytes : ws_max;
+    const size_t want = grow_to(ws_max, had, room ? left : 0);
+    if (malloc_grown(&B.ws, want, ws_max, &B.ws_bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(ctx, MILS_ERR_OOM, "hipMalloc of batch workspace failed");
     }
-    B.ws_bytes = ws_max;
   }
   if (B.status_cap < (size_t)nstatus) {
     if (B.status_host) (void)hipHostFree(B.status_host);
