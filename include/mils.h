@@ -353,6 +353,10 @@ int mils_server_destroy(mils_server *srv);
  */
 enum { MILS_NUM_STAGES = 9 };
 int mils_profile_enable(mils_context *ctx, int enable);
+/* Stages timed while profiling is enabled: bit s for stage s (default: all).
+ * Each timed stage adds two events per call; timing one stage leaves the rest
+ * of the call as it runs unprofiled. */
+int mils_profile_stages(mils_context *ctx, uint32_t mask);
 const char *mils_profile_stage_name(int stage);
 int mils_profile_read(mils_context *ctx, double *ms_total, int64_t *launches);
 

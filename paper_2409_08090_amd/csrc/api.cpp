@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -127,6 +128,7 @@ struct mils_context {
   bool have_pending = false;
   // per-stage event timing
   bool prof = false;
+  uint32_t prof_mask = ~0u;  // stages timed while prof is on
   hipEvent_t prof_begin[kNumStages] = {};
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_recs;
   std::vector<hipEvent_t> prof_pool;
@@ -135,6 +137,16 @@ struct mils_context {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   BatchState batch;
+  // the single-series call captured as a HIP graph: its key (arguments,
+  // workspace layout, plan) was seen on the previous call; replayed while
+  // the calls repeat it
+  struct SingleGraph {
+    bool have_key = false;
+    unsigned char key[sizeof(CallArgs) + sizeof(Work) + sizeof(void*)] = {};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+  } sg;
   // batch autotuner: (N_f band, eps, precision) -> (sigma, largest spreading tile)
   std::map<std::tuple<int, double, int>, std::pair<double, int>> tuned;
 };
@@ -310,6 +322,7 @@ hipEvent_t prof_event(mils_context* ctx) {
 
 void prof_hook(void* ud, int stage, int begin, hipStream_t s) {
   mils_context* ctx = static_cast<mils_context*>(ud);
+  if (!((ctx->prof_mask >> stage) & 1u)) return;
   hipEvent_t e = prof_event(ctx);
   if (!e) return;
   (void)hipEventRecord(e, s);
@@ -321,6 +334,53 @@ void prof_hook(void* ud, int stage, int begin, hipStream_t s) {
   } else {
     ctx->prof_pool.push_back(e);
   }
+}
+
+// Graphs for repeated single-series calls (MILS_GRAPH=0 turns them off).
+bool graphs_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("MILS_GRAPH");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
+// The launches of one single-series call: the first time a key repeats, they
+// are captured (on a context-owned stream; the fork to the second stream and
+// the join become graph edges) and the graph replays for as long as the key
+// repeats; a new key launches directly.  Launching a graph costs one call
+// and lets the runtime queue the kernels back to back.
+hipError_t launch_single_graph(mils_context* ctx, const CallArgs& a, const Plan& plan,
+                               const Work& w, hipStream_t stream, const AuxStream& aux) {
+  auto& G = ctx->sg;
+  unsigned char key[sizeof(G.key)];
+  std::memcpy(key, &a, sizeof(CallArgs));
+  std::memcpy(key + sizeof(CallArgs), &w, sizeof(Work));
+  const Plan* pp = &plan;
+  std::memcpy(key + sizeof(CallArgs) + sizeof(Work), &pp, sizeof(void*));
+  const bool same = G.have_key && std::memcmp(key, G.key, sizeof(key)) == 0;
+  if (!same) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    if (G.graph) (void)hipGraphDestroy(G.graph);
+    G.exec = nullptr;
+    G.graph = nullptr;
+    std::memcpy(G.key, key, sizeof(key));
+    G.have_key = true;
+    return launch_path(a, plan, w, stream, nullptr, &aux);
+  }
+  hipError_t he = hipSuccess;
+  if (!G.exec) {
+    if (!G.cap) he = hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      hipError_t le = launch_path(a, plan, w, G.cap, nullptr, &aux);
+      he = hipStreamEndCapture(G.cap, &G.graph);
+      if (le != hipSuccess) he = le;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) return he;
+  }
+  return hipGraphLaunch(G.exec, stream);
 }
 
 // Common body of the single-series calls.
@@ -346,7 +406,8 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   w.tw = pe->tw;
   w.inv_phihat = pe->inv_phihat;
 
-  CallArgs a{};
+  CallArgs a;
+  std::memset(&a, 0, sizeof(a));  // the bytes serve as a graph key
   a.t = t;
   a.y = y;
   a.dy = dy;
@@ -366,7 +427,11 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.sums = sums;
   StageHook hook{prof_hook, ctx};
   AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
-  he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr, ctx->aux ? &aux : nullptr);
+  if (!ctx->prof && ctx->aux && graphs_enabled()) {
+    he = launch_single_graph(ctx, a, plan, w, stream, aux);
+  } else {
+    he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr, ctx->aux ? &aux : nullptr);
+  }
   if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
   ctx->last_stats = w.stats;
   ctx->last_stream = stream;
@@ -448,6 +513,9 @@ int mils_context_destroy(mils_context* ctx) {
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
     free_batch_state(ctx->batch);
+    if (ctx->sg.exec) (void)hipGraphExecDestroy(ctx->sg.exec);
+    if (ctx->sg.graph) (void)hipGraphDestroy(ctx->sg.graph);
+    if (ctx->sg.cap) (void)hipStreamDestroy(ctx->sg.cap);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
@@ -1235,6 +1303,12 @@ int mils_profile_enable(mils_context* ctx, int enable) {
     ctx->prof_pool.push_back(std::get<2>(r));
   }
   ctx->prof_recs.clear();
+  return MILS_OK;
+}
+
+int mils_profile_stages(mils_context* ctx, uint32_t mask) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  ctx->prof_mask = mask;
   return MILS_OK;
 }
 

@@ -121,6 +121,7 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
     "mils_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "mils_profile_stage_name": ([ctypes.c_int], ctypes.c_char_p),
+    "mils_profile_stages": ([_P, ctypes.c_uint32], ctypes.c_int),
     "mils_profile_read": ([_P, _D, _I64P], ctypes.c_int),
     "mils_server_create": ([ctypes.c_int, ctypes.POINTER(mils_server_config), ctypes.POINTER(_P)],
                            ctypes.c_int),
@@ -188,8 +189,15 @@ class Context:
     def last_error(self) -> str:
         return load().mils_last_error(self.handle).decode()
 
-    def profile_enable(self, enable: bool = True):
-        self.check(load().mils_profile_enable(self.handle, int(bool(enable))))
+    def profile_enable(self, enable: bool = True, stages=None):
+        """Per-stage HIP-event timing; stages: names to time (None: all)."""
+        lib = load()
+        mask = 0xFFFFFFFF
+        if stages is not None:
+            names = [lib.mils_profile_stage_name(i).decode() for i in range(MILS_NUM_STAGES)]
+            mask = sum(1 << names.index(n) for n in stages)
+        self.check(lib.mils_profile_stages(self.handle, mask))
+        self.check(lib.mils_profile_enable(self.handle, int(bool(enable))))
 
     def profile_read(self) -> dict:
         """{stage name: (total ms, launches)} since the last read / enable."""

@@ -293,3 +293,38 @@ def test_deterministic_flag_rejected_outside_single_series():
         dfs.ctypes.data_as(mils._D), ctypes.byref(prm), ctypes.c_void_p(bout.data_ptr()), None,
         None)
     assert rc == mils.MILS_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------- graph replays
+def test_repeated_call_replays_match_eager_result():
+    """A call repeated with the same arguments is captured as a HIP graph on
+    its second occurrence and replayed afterwards; every replay, with eager
+    work and synchronisations in between, must give the eager result, and a
+    call with other arguments in between must not disturb it."""
+    c = workloads.single_large(seed=3, nd=120_000, span_years=3)
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    out = torch.empty(c.nf, dtype=torch.float64, device="cuda")
+    other = workloads.uniform_series(seed=8, nd=900, nf=7000, span=30.0)
+    ot, oy, od = dev(other.t), dev(other.y), dev(other.dy)
+    ctx = mils.Context(0)
+
+    def run():
+        mils.periodogram(t, y, dy, c.f0, c.df, c.nf, out=out, ctx=ctx)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().copy()
+
+    eager = run()                      # first occurrence: direct launches
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=np.arange(0, c.nf, 997))
+    assert rel_err(eager[::997], ref) <= 1e-8
+    for i in range(5):                 # second: capture; then replays
+        scratch = torch.randn(1 << 20, device="cuda") * 2.0  # eager work between replays
+        torch.cuda.synchronize()
+        r = run()
+        assert np.max(np.abs(r - eager)) <= 1e-13 * np.max(np.abs(eager)), i
+        del scratch
+        if i == 2:                     # another key in between, then back
+            p2 = mils.periodogram(ot, oy, od, other.f0, other.df, other.nf, ctx=ctx)
+            torch.cuda.synchronize()
+            ref2 = oracle.periodogram(other.t, other.y, other.dy, other.f0, other.df,
+                                      nf=other.nf)
+            assert rel_err(p2.cpu().numpy(), ref2) <= 1e-8
