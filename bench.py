@@ -292,6 +292,7 @@ def main():
         lat = lat_ms(tickets)
         wall = time.perf_counter() - s0
         ss = srv.stats()
+        lane_err = srv.last_error()
         srv.close()
         done_sums = float(sum(float(pool[pi].nd) * float(pool[pi].nf) for pi in picks))
         extra["serving"] = {"rate_req_s": rate, "seconds": dur, "offered": int(arrivals.size),
@@ -304,7 +305,10 @@ def main():
                                        "p50_ms": round(float(np.percentile(cold, 50)), 3),
                                        "max_ms": round(float(cold.max()), 3)},
                             "mean_batch": round(ss["mean_batch"], 2), "batches": ss["batches"],
-                            "peak_inflight_bytes": ss["peak_inflight_bytes"]}
+                            "peak_inflight_bytes": ss["peak_inflight_bytes"],
+                            "failed": ss["failed"], "dead_lanes": ss["dead_lanes"]}
+        if lane_err:
+            extra["serving"]["lane_error"] = lane_err
 
     # the brute-force comparison (Sec. 3.1): every sum term by term in FP64 on
     # the first 1.2e6 frequencies of the same curve (last of the GPU legs: a

@@ -132,6 +132,18 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context **ou
 /* Release the context and its device workspace (synchronises its device). */
 int mils_context_destroy(mils_context *ctx);
 
+/* Graph replay of repeated single-series calls (mils_periodogram[_async],
+ * mils_trig_sums).  While enabled (the default, unless the environment sets
+ * MILS_GRAPH=0), a call whose arguments, workspace and plan repeat those of
+ * the context's previous call is captured as a HIP graph, and the graph is
+ * replayed for as long as they keep repeating; a call on a stream that is
+ * itself being captured launches directly.  On a new key the host waits for
+ * the previous replay before releasing its graph.  A context whose calls
+ * seldom repeat (a server lane) turns it off: each capture costs more than
+ * a replay saves.  Disabling releases the context's graph (after its last
+ * replay has finished). */
+int mils_context_set_graphs(mils_context *ctx, int enable);
+
 /* Fill *out with the plan for a periodogram of nd points with parameters p.
  * Host-only; valid on a host-only context. */
 int mils_plan_info(mils_context *ctx, int64_t nd, const mils_params *p, mils_plan_desc *out);
@@ -315,6 +327,8 @@ typedef struct {
   double latency_p50_ms, latency_p99_ms, latency_max_ms; /* submit -> result on host */
   double sums_per_s;  /* sum of nd*nf over completed requests / (last done - first submit) */
   double mean_batch;  /* requests per batch */
+  uint64_t failed;     /* completed requests whose status is not MILS_OK */
+  uint64_t dead_lanes; /* lanes stopped by a device error (their context is unusable) */
 } mils_server_counters;
 
 /* Create a server on HIP device `device` (cfg may be NULL for defaults). */
@@ -332,6 +346,10 @@ int mils_server_wait(mils_server *srv, uint64_t ticket, int64_t timeout_us);
  * the request's status. */
 int mils_server_take(mils_server *srv, uint64_t ticket, double *power, mils_request_stats *st);
 int mils_server_stats(mils_server *srv, mils_server_counters *out);
+/* Message of the first device error that stopped a lane ("" if none).  Once
+ * every lane has stopped, pending requests complete with MILS_ERR_DEVICE and
+ * submit returns MILS_ERR_DEVICE. */
+const char *mils_server_last_error(mils_server *srv);
 /* Stop the lanes; requests not yet done are cancelled (their tickets become
  * invalid).  Waits for batches already on the device. */
 int mils_server_destroy(mils_server *srv);

@@ -141,11 +141,13 @@ struct mils_context {
   // workspace layout, plan) was seen on the previous call; replayed while
   // the calls repeat it
   struct SingleGraph {
+    bool enabled = true;
     bool have_key = false;
     unsigned char key[sizeof(CallArgs) + sizeof(Work) + sizeof(void*)] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each replay
   } sg;
   // batch autotuner: (N_f band, eps, precision) -> (sigma, largest spreading tile)
   std::map<std::tuple<int, double, int>, std::pair<double, int>> tuned;
@@ -345,6 +347,19 @@ bool graphs_enabled() {
   return on;
 }
 
+// Releases the context's single-series graph once its last replay has
+// finished (the replay may still be queued when the caller did not wait).
+void release_single_graph(mils_context* ctx) {
+  auto& G = ctx->sg;
+  if (G.exec) {
+    if (G.done) (void)hipEventSynchronize(G.done);
+    (void)hipGraphExecDestroy(G.exec);
+  }
+  if (G.graph) (void)hipGraphDestroy(G.graph);
+  G.exec = nullptr;
+  G.graph = nullptr;
+}
+
 // The launches of one single-series call: the first time a key repeats, they
 // are captured (on a context-owned stream; the fork to the second stream and
 // the join become graph edges) and the graph replays for as long as the key
@@ -353,6 +368,10 @@ bool graphs_enabled() {
 hipError_t launch_single_graph(mils_context* ctx, const CallArgs& a, const Plan& plan,
                                const Work& w, hipStream_t stream, const AuxStream& aux) {
   auto& G = ctx->sg;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t he = hipStreamIsCapturing(stream, &cs);
+  if (he != hipSuccess) return he;
+  if (cs != hipStreamCaptureStatusNone) return launch_path(a, plan, w, stream, nullptr, &aux);
   unsigned char key[sizeof(G.key)];
   std::memcpy(key, &a, sizeof(CallArgs));
   std::memcpy(key + sizeof(CallArgs), &w, sizeof(Work));
@@ -360,17 +379,14 @@ hipError_t launch_single_graph(mils_context* ctx, const CallArgs& a, const Plan&
   std::memcpy(key + sizeof(CallArgs) + sizeof(Work), &pp, sizeof(void*));
   const bool same = G.have_key && std::memcmp(key, G.key, sizeof(key)) == 0;
   if (!same) {
-    if (G.exec) (void)hipGraphExecDestroy(G.exec);
-    if (G.graph) (void)hipGraphDestroy(G.graph);
-    G.exec = nullptr;
-    G.graph = nullptr;
+    release_single_graph(ctx);
     std::memcpy(G.key, key, sizeof(key));
     G.have_key = true;
     return launch_path(a, plan, w, stream, nullptr, &aux);
   }
-  hipError_t he = hipSuccess;
   if (!G.exec) {
     if (!G.cap) he = hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking);
+    if (he == hipSuccess && !G.done) he = hipEventCreateWithFlags(&G.done, hipEventDisableTiming);
     if (he == hipSuccess) he = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
     if (he == hipSuccess) {
       hipError_t le = launch_path(a, plan, w, G.cap, nullptr, &aux);
@@ -380,7 +396,9 @@ hipError_t launch_single_graph(mils_context* ctx, const CallArgs& a, const Plan&
     if (he == hipSuccess) he = hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0);
     if (he != hipSuccess) return he;
   }
-  return hipGraphLaunch(G.exec, stream);
+  he = hipGraphLaunch(G.exec, stream);
+  if (he == hipSuccess) he = hipEventRecord(G.done, stream);
+  return he;
 }
 
 // Common body of the single-series calls.
@@ -427,7 +445,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.sums = sums;
   StageHook hook{prof_hook, ctx};
   AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
-  if (!ctx->prof && ctx->aux && graphs_enabled()) {
+  if (!ctx->prof && ctx->aux && ctx->sg.enabled && graphs_enabled()) {
     he = launch_single_graph(ctx, a, plan, w, stream, aux);
   } else {
     he = launch_path(a, plan, w, stream, ctx->prof ? &hook : nullptr, ctx->aux ? &aux : nullptr);
@@ -513,9 +531,9 @@ int mils_context_destroy(mils_context* ctx) {
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
     free_batch_state(ctx->batch);
-    if (ctx->sg.exec) (void)hipGraphExecDestroy(ctx->sg.exec);
-    if (ctx->sg.graph) (void)hipGraphDestroy(ctx->sg.graph);
+    release_single_graph(ctx);
     if (ctx->sg.cap) (void)hipStreamDestroy(ctx->sg.cap);
+    if (ctx->sg.done) (void)hipEventDestroy(ctx->sg.done);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
@@ -1303,6 +1321,17 @@ int mils_profile_enable(mils_context* ctx, int enable) {
     ctx->prof_pool.push_back(std::get<2>(r));
   }
   ctx->prof_recs.clear();
+  return MILS_OK;
+}
+
+int mils_context_set_graphs(mils_context* ctx, int enable) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  ctx->sg.enabled = enable != 0;
+  if (!ctx->sg.enabled && ctx->device >= 0) {
+    (void)hipSetDevice(ctx->device);
+    release_single_graph(ctx);
+    ctx->sg.have_key = false;
+  }
   return MILS_OK;
 }
 

@@ -111,6 +111,8 @@ struct mils_server {
   bool stop = false;
   uint64_t inflight = 0, peak = 0;
   uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0;
+  uint64_t failed = 0, dead_lanes = 0;
+  std::string lane_error;  // message of the first device error that ended a lane
   std::vector<double> lat_ms;
   double first_submit = -1.0, last_done = 0.0, sums_done = 0.0;
   std::vector<std::unique_ptr<Lane>> lanes;
@@ -119,6 +121,7 @@ struct mils_server {
   void lane_loop(Lane* L);
   void run_batch(Lane* L, std::vector<Request*>& batch);
   void run_single(Lane* L, Request* r);
+  void lane_died(Lane* L);
 };
 
 namespace {
@@ -216,6 +219,29 @@ void mils_server::run_batch(Lane* L, std::vector<Request*>& batch) {
   if (rc == MILS_ERR_DEVICE) L->dead = true;
 }
 
+// A lane whose context took a device error stops; once no lane is left, the
+// pending requests end with MILS_ERR_DEVICE instead of waiting forever.
+// Called with mu held.
+void mils_server::lane_died(Lane* L) {
+  ++dead_lanes;
+  if (lane_error.empty()) {
+    const char* m = mils_last_error(L->ctx);
+    lane_error = (m && m[0]) ? m : "device error";
+  }
+  if (dead_lanes < lanes.size()) return;
+  const double t = now();
+  for (uint64_t tk : pending) {
+    Request* r = reqs[tk].get();
+    r->state = MILS_REQ_DONE;
+    r->status = MILS_ERR_DEVICE;
+    r->start_s = r->done_s = t;
+    ++completed;
+    ++failed;
+  }
+  pending.clear();
+  cv_done.notify_all();
+}
+
 void mils_server::lane_loop(Lane* L) {
   (void)hipSetDevice(device);
   const auto tick = std::chrono::microseconds(cfg.tick_us);
@@ -291,7 +317,9 @@ void mils_server::lane_loop(Lane* L) {
       ++completed;
       lat_ms.push_back((t_done - r->submit_s) * 1e3);
       if (r->status == MILS_OK) sums_done += (double)r->nd * (double)r->p.nf;
+      else ++failed;
     }
+    if (L->dead) lane_died(L);
     last_done = t_done;
     cv_done.notify_all();
     cv_work.notify_all();
@@ -323,6 +351,8 @@ int mils_server_create(int device, const mils_server_config* cfg, mils_server** 
   for (int i = 0; i < c.lanes; ++i) {
     auto L = std::make_unique<Lane>();
     int rc = mils_context_create(device, 0, &L->ctx);
+    // a lane's single-series calls seldom repeat their arguments
+    if (rc == MILS_OK) rc = mils_context_set_graphs(L->ctx, 0);
     if (rc == MILS_OK && hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
       rc = MILS_ERR_DEVICE;
     if (rc != MILS_OK) {
@@ -360,6 +390,7 @@ int mils_server_submit(mils_server* srv, const mils_request* req, uint64_t* tick
   r->nd = req->nd;
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->stop) return MILS_ERR_CANCELLED;
+  if (srv->dead_lanes == srv->lanes.size()) return MILS_ERR_DEVICE;
   if (rb + (uint64_t)(24 * req->nd + 8 * req->params.nf) > srv->cfg.hbm_budget_bytes) {
     ++srv->rejected;
     return MILS_ERR_OOM;
@@ -425,6 +456,12 @@ int mils_server_take(mils_server* srv, uint64_t ticket, double* power, mils_requ
   return r->status;
 }
 
+const char* mils_server_last_error(mils_server* srv) {
+  if (!srv) return "";
+  std::lock_guard<std::mutex> lk(srv->mu);
+  return srv->lane_error.c_str();
+}
+
 int mils_server_stats(mils_server* srv, mils_server_counters* out) {
   if (!srv || !out) return MILS_ERR_INVALID_ARG;
   std::vector<double> lat;
@@ -437,6 +474,8 @@ int mils_server_stats(mils_server* srv, mils_server_counters* out) {
     out->inflight_bytes = srv->inflight;
     out->peak_inflight_bytes = srv->peak;
     out->mean_batch = srv->batches ? (double)srv->batched_reqs / (double)srv->batches : 0.0;
+    out->failed = srv->failed;
+    out->dead_lanes = srv->dead_lanes;
     const double span = srv->last_done - srv->first_submit;
     out->sums_per_s = span > 0 ? srv->sums_done / span : 0.0;
     lat = srv->lat_ms;

@@ -70,7 +70,8 @@ class mils_server_counters(ctypes.Structure):
                 ("inflight_bytes", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64),
                 ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
                 ("latency_max_ms", ctypes.c_double), ("sums_per_s", ctypes.c_double),
-                ("mean_batch", ctypes.c_double)]
+                ("mean_batch", ctypes.c_double), ("failed", ctypes.c_uint64),
+                ("dead_lanes", ctypes.c_uint64)]
 
 
 class MilsError(RuntimeError):
@@ -92,6 +93,7 @@ SIGNATURES = {
     "mils_last_error": ([_P], ctypes.c_char_p),
     "mils_context_create": ([ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)], ctypes.c_int),
     "mils_context_destroy": ([_P], ctypes.c_int),
+    "mils_context_set_graphs": ([_P, ctypes.c_int], ctypes.c_int),
     "mils_plan_info": ([_P, ctypes.c_int64, ctypes.POINTER(mils_params),
                         ctypes.POINTER(mils_plan_desc)], ctypes.c_int),
     "mils_batch_tuning": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
@@ -132,6 +134,7 @@ SIGNATURES = {
     "mils_server_take": ([_P, ctypes.c_uint64, _P, ctypes.POINTER(mils_request_stats)],
                          ctypes.c_int),
     "mils_server_stats": ([_P, ctypes.POINTER(mils_server_counters)], ctypes.c_int),
+    "mils_server_last_error": ([_P], ctypes.c_char_p),
     "mils_server_destroy": ([_P], ctypes.c_int),
 }
 
@@ -188,6 +191,10 @@ class Context:
 
     def last_error(self) -> str:
         return load().mils_last_error(self.handle).decode()
+
+    def set_graphs(self, enable: bool):
+        """Graph replay of repeated single-series calls (on by default)."""
+        self.check(load().mils_context_set_graphs(self.handle, int(bool(enable))))
 
     def profile_enable(self, enable: bool = True, stages=None):
         """Per-stage HIP-event timing; stages: names to time (None: all)."""
@@ -528,6 +535,10 @@ class Server:
         if rc != MILS_OK:
             raise MilsError(rc, "mils_server_stats failed")
         return {f: getattr(c, f) for f, _ in mils_server_counters._fields_}
+
+    def last_error(self) -> str:
+        """Message of the first device error that stopped a lane ("" if none)."""
+        return load().mils_server_last_error(self.handle).decode()
 
     def close(self):
         if self.handle:

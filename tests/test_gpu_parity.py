@@ -328,3 +328,36 @@ def test_repeated_call_replays_match_eager_result():
             ref2 = oracle.periodogram(other.t, other.y, other.dy, other.f0, other.df,
                                       nf=other.nf)
             assert rel_err(p2.cpu().numpy(), ref2) <= 1e-8
+
+
+def test_async_replays_with_key_changes_and_graphs_off():
+    """Asynchronous calls without waits in between: replays of one key, then
+    another key (the context releases the graph only after its last replay
+    has finished), then the first key again; every output must equal the
+    eager result.  With graph replay switched off the same calls launch
+    directly and give the same results."""
+    c = workloads.single_large(seed=5, nd=80_000, span_years=2)
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    other = workloads.uniform_series(seed=9, nd=1500, nf=9000, span=25.0)
+    ot, oy, od = dev(other.t), dev(other.y), dev(other.dy)
+    ctx = mils.Context(0)
+    eager = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx).cpu().numpy()
+    eager2 = mils.periodogram(ot, oy, od, other.f0, other.df, other.nf, ctx=ctx).cpu().numpy()
+    for graphs in (True, False):
+        ctx.set_graphs(graphs)
+        outs = [torch.empty(c.nf, dtype=torch.float64, device="cuda") for _ in range(4)]
+        out2 = torch.empty(other.nf, dtype=torch.float64, device="cuda")
+        for o in outs[:3]:  # same key except the output pointer: direct launches
+            mils.periodogram(t, y, dy, c.f0, c.df, c.nf, out=o, ctx=ctx, sync=False)
+        for _ in range(3):  # identical calls: capture, then replays
+            mils.periodogram(t, y, dy, c.f0, c.df, c.nf, out=outs[3], ctx=ctx, sync=False)
+        mils.periodogram(ot, oy, od, other.f0, other.df, other.nf, out=out2, ctx=ctx, sync=False)
+        for _ in range(2):
+            mils.periodogram(t, y, dy, c.f0, c.df, c.nf, out=outs[0], ctx=ctx, sync=False)
+        assert mils.context_status(ctx) == mils.MILS_OK
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert np.max(np.abs(o.cpu().numpy() - eager)) <= 1e-13 * np.max(np.abs(eager)), \
+                (graphs, i)
+        assert np.max(np.abs(out2.cpu().numpy() - eager2)) <= 1e-13 * np.max(np.abs(eager2))
+    ctx.close()

@@ -71,6 +71,7 @@ def test_same_result_alone_and_in_a_mix():
     print("[server] stats", {k: s[k] for k in ("completed", "batches", "mean_batch",
                                                "latency_p50_ms", "latency_p99_ms")}, flush=True)
     assert s["completed"] == s["submitted"] == 302 + 2
+    assert s["failed"] == 0 and s["dead_lanes"] == 0
     assert max(sizes) > 1  # requests were batched together
     srv.close()
 
@@ -120,6 +121,32 @@ def test_large_request_and_per_request_errors():
     assert rel(p, oracle.periodogram(ok.t, ok.y, ok.dy, ok.f0, ok.df, nf=ok.nf)) <= 1e-8
     # an unknown ticket is rejected
     assert srv.poll(10 ** 9)[0] == mils.MILS_ERR_INVALID_ARG
+    srv.close()
+
+
+def test_repeated_large_requests_beside_batches():
+    """The same large request over and over on several lanes, mixed with small
+    batched requests: every request succeeds, no lane stops, and the large
+    results equal the first one."""
+    rng = np.random.default_rng(5)
+    srv = mils.Server(0, lanes=3)
+    big = workloads.single_large(seed=6, nd=30_000, span_years=2)  # single path
+    small = [workloads.batch_curve(rng, int(rng.integers(100, 4000))) for _ in range(20)]
+    tks = []
+    for i in range(24):
+        tks.append((submit(srv, big, "fp64"), big))
+        tks.append((submit(srv, small[i % len(small)], "fp32"), small[i % len(small)]))
+    first = None
+    for tk, c in tks:
+        rc, p, _ = result(srv, tk, c.nf)
+        assert rc == mils.MILS_OK, (rc, srv.last_error())
+        if c is big:
+            if first is None:
+                first = p
+            assert np.max(np.abs(p - first)) <= 1e-12 * np.max(np.abs(first))
+    s = srv.stats()
+    assert s["failed"] == 0 and s["dead_lanes"] == 0, srv.last_error()
+    assert srv.last_error() == ""
     srv.close()
 
 
