@@ -202,6 +202,16 @@ def test_server_config_and_device_checks():
     assert lib.mils_server_create(0, None, None) == mils.MILS_ERR_INVALID_ARG
     assert lib.mils_server_submit(None, None, None) == mils.MILS_ERR_INVALID_ARG
     assert lib.mils_server_destroy(None) == mils.MILS_ERR_INVALID_ARG
+    assert lib.mils_server_last_error(None) == b""
+
+
+def test_graph_switch_on_host_context():
+    lib = mils.load()
+    assert lib.mils_context_set_graphs(None, 0) == mils.MILS_ERR_INVALID_ARG
+    ctx = mils.Context(-1)  # host-only: nothing to release
+    ctx.set_graphs(False)
+    ctx.set_graphs(True)
+    ctx.close()
 
 
 @pytest.mark.parametrize("nf,eps,prec", [(12_000_000, 1e-9, "fp64"), (100_000, 1e-12, "fp64"),
