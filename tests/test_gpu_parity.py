@@ -361,3 +361,64 @@ def test_async_replays_with_key_changes_and_graphs_off():
                 (graphs, i)
         assert np.max(np.abs(out2.cpu().numpy() - eager2)) <= 1e-13 * np.max(np.abs(eager2))
     ctx.close()
+
+
+# ---------------------------------------------------------------- maximum size
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_maximum_frequency_count(precision):
+    """N_f = 2^28, the largest count the library accepts: in FP64 a four-pass
+    plan (two middle passes through HBM), in FP32 a three-pass plan with
+    1024-point passes (n = 4.0e8 cells).  Checked against the oracle at both
+    band edges, around the fold of the fine grid (k near N_f / 2), at the
+    signal's peak and at random frequencies."""
+    nf, nd = 2 ** 28, 20_000
+    eps = {"fp64": 1e-9, "fp32": 1e-5}[precision]
+    f0, df = 1e-3, 1e-4
+    d = mils.plan_info(nd, nf, eps, precision, f0, df)
+    print(f"[max N_f {precision}] n={d['n']} len={d['len'][:d['npass']]} "
+          f"workspace {d['workspace_bytes'] / 2**30:.1f} GiB", flush=True)
+    if precision == "fp64":
+        assert d["npass"] == 4
+    rng = np.random.default_rng(41)
+    t = np.sort(rng.uniform(0.0, 2000.0, nd))
+    y = np.sin(2 * np.pi * 0.37 * t) + rng.normal(0.0, 0.5, nd)
+    dy = rng.uniform(0.3, 0.8, nd)
+    ctx = mils.Context(0)
+    p = mils.periodogram(dev(t), dev(y), dev(dy), f0, df, nf, eps=eps, precision=precision,
+                         ctx=ctx)
+    K = nf // 2
+    k = np.unique(np.concatenate([np.arange(64), np.arange(nf - 64, nf), np.arange(K - 32, K + 32),
+                                  rng.integers(0, nf, 300), [int(round((0.37 - f0) / df))]]))
+    got = p[torch.from_numpy(k).cuda()].cpu().numpy()
+    del p
+    ctx.close()
+    torch.cuda.empty_cache()
+    ref = oracle.periodogram(t, y, dy, f0, df, k=k)
+    err = rel_err(got, ref)
+    print(f"[max N_f {precision}] {k.size} frequencies, max-normalised {err:.3e}", flush=True)
+    assert err <= {"fp64": 1e-8, "fp32": 1e-4}[precision]
+
+
+@pytest.mark.parametrize("sorted_t", [True, False])
+def test_large_point_count(sorted_t):
+    """N_d = 2^25 points (sorted: binning by search; unsorted: the counting
+    sort of every point into its bin), on a grid of 10^5 frequencies, against
+    the oracle at sampled frequencies including the peak."""
+    nd, nf = 2 ** 25, 100_000
+    rng = np.random.default_rng(43)
+    t = rng.uniform(0.0, 3000.0, nd)
+    if sorted_t:
+        t.sort()
+    y = np.sin(2 * np.pi * 0.21 * t) + rng.normal(0.0, 2.0, nd)
+    dy = rng.uniform(0.5, 2.0, nd)
+    f0, df = 2e-3, 1e-4
+    ctx = mils.Context(0)
+    p = mils.periodogram(dev(t), dev(y), dev(dy), f0, df, nf, ctx=ctx).cpu().numpy()
+    ctx.close()
+    k = np.unique(np.concatenate([np.arange(8), np.arange(nf - 8, nf), rng.integers(0, nf, 24),
+                                  [int(round((0.21 - f0) / df))]]))
+    ref = oracle.periodogram(t, y, dy, f0, df, k=k)
+    err = rel_err(p[k], ref)
+    print(f"[N_d=2^25 sorted={sorted_t}] {k.size} frequencies, max-normalised {err:.3e}",
+          flush=True)
+    assert err <= TOL["fp64"]
