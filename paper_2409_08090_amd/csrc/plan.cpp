@@ -52,15 +52,12 @@ static int big_rows(int L, int64_t P, int G, int prec) {
   }
   return 0;
 }
-// Big passes are opt-in (MILS_FFT_BIG=1): one workgroup per CU cannot
-// overlap its loads, transform and stores, and measured slower than three
-// small passes on the 1.5e7-cell grids.
+// Big passes are opt-in (MILS_FFT_BIG=1, read whenever a plan is made):
+// one workgroup per CU cannot overlap its loads, transform and stores, and
+// measured slower than three small passes on the 1.5e7-cell grids.
 static bool big_enabled() {
-  static const bool on = [] {
-    const char* e = std::getenv("MILS_FFT_BIG");
-    return e && e[0] == '1';
-  }();
-  return on;
+  const char* e = std::getenv("MILS_FFT_BIG");
+  return e && e[0] == '1';
 }
 
 std::vector<int64_t> smooth_in_range(int64_t lo, int64_t hi) {

@@ -422,3 +422,36 @@ def test_large_point_count(sorted_t):
     print(f"[N_d=2^25 sorted={sorted_t}] {k.size} frequencies, max-normalised {err:.3e}",
           flush=True)
     assert err <= TOL["fp64"]
+
+
+# ---------------------------------------------------------------- big passes
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_big_pass_option(precision, monkeypatch):
+    """MILS_FFT_BIG=1 (read when a plan is made): the full-size curve through
+    two passes of 1024-thread workgroups with up to 160 KB of LDS and
+    two-level twiddle tables gives the default three-pass result, and matches
+    the oracle on sampled frequencies."""
+    c = workloads.single_large(seed=1)
+    eps = EPS[precision]
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    ctx = mils.Context(0)
+    base = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, eps=eps, precision=precision,
+                            ctx=ctx).cpu().numpy()
+    ctx.close()
+    monkeypatch.setenv("MILS_FFT_BIG", "1")
+    d = mils.plan_info(c.nd, c.nf, eps, precision, c.f0, c.df)
+    print(f"[big passes {precision}] len={d['len'][:d['npass']]} LDS first "
+          f"{d['first_lds_bytes']} last {d['last_lds_bytes']}", flush=True)
+    assert d["big"] == 1 and d["npass"] == 2
+    ctx = mils.Context(0)
+    big = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, eps=eps, precision=precision,
+                           ctx=ctx).cpu().numpy()
+    ctx.close()
+    monkeypatch.delenv("MILS_FFT_BIG")
+    rng = np.random.default_rng(12)
+    k = np.unique(np.concatenate([rng.integers(0, c.nf, 60), np.arange(20), np.arange(c.nf - 20, c.nf),
+                                  np.argsort(base)[-10:]]))
+    ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+    d_base, d_ref = rel_err(big, base), rel_err(big[k], ref)
+    print(f"[big passes {precision}] vs default path {d_base:.3e}, vs oracle {d_ref:.3e}", flush=True)
+    assert d_base <= TOL[precision] and d_ref <= TOL[precision]
