@@ -151,3 +151,22 @@ def test_large_shared_weights_sampled():
         print(f"[shared_t large series {i}] {k.size} frequencies, max-normalised {err:.3e}",
               flush=True)
         assert err <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_big_pass_option_full_size(precision, monkeypatch):
+    """MILS_FFT_BIG=1 (read when a plan is made) on four full-size series
+    sharing their times: the two-pass plan of 1024-thread workgroups gives
+    the default plan's result for every series."""
+    s = workloads.shared_times(seed=59, nd=1_000_000, nseries=4)
+    base = run(s, precision, "shared")
+    monkeypatch.setenv("MILS_FFT_BIG", "1")
+    ctx = mils.Context(0)  # a context of its own: plans are cached per context
+    assert mils.plan_info(s.t.size, s.nf, EPS[precision], precision, s.f0, s.df)["big"] == 1
+    big = run(s, precision, "shared", ctx=ctx)
+    ctx.close()
+    monkeypatch.delenv("MILS_FFT_BIG")
+    for i in range(s.nseries):
+        err = rel_err(big[i], base[i])
+        print(f"[shared_t big passes {precision} series {i}] vs default plan {err:.3e}", flush=True)
+        assert err <= TOL[precision]
