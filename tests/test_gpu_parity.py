@@ -455,3 +455,38 @@ def test_big_pass_option(precision, monkeypatch):
     d_base, d_ref = rel_err(big, base), rel_err(big[k], ref)
     print(f"[big passes {precision}] vs default path {d_base:.3e}, vs oracle {d_ref:.3e}", flush=True)
     assert d_base <= TOL[precision] and d_ref <= TOL[precision]
+
+
+# ---------------------------------------------------------------- stage timing
+def test_stage_profiling():
+    """Per-stage HIP-event timing: every stage of a three-pass periodogram is
+    timed (the first FFT pass as two launches, one per stream), a stage mask
+    times only its stages, a read clears the accumulators, and the results
+    with timing on agree to rounding with those with it off."""
+    c = workloads.single_large(seed=3, nd=120_000, span_years=3)
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    ctx = mils.Context(0)
+    assert mils.plan_info(c.nd, c.nf, 1e-9, "fp64", c.f0, c.df)["npass"] == 3
+    plain = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx).cpu().numpy()
+    ctx.profile_enable(True)
+    reps = 3
+    for _ in range(reps):
+        timed = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx).cpu().numpy()
+    prof = ctx.profile_read()
+    # the LDS accumulation order of the spread may differ between calls
+    assert np.max(np.abs(timed - plain)) <= 1e-13 * np.max(np.abs(plain))
+    expect = {"stats": 1, "bin_sort": 1, "spread_f": 1, "spread_2f": 1, "fft_pass_0": 2,
+              "fft_pass_1": 1, "fft_last_power": 1, "lowfreq": 1}
+    assert set(prof) == set(expect), prof
+    for name, per_call in expect.items():
+        ms, n = prof[name]
+        assert n == reps * per_call and ms > 0.0, (name, prof[name])
+    assert ctx.profile_read() == {}  # cleared by the read
+    ctx.profile_enable(True, stages=["fft_pass_1", "fft_last_power"])
+    mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx)
+    prof = ctx.profile_read()
+    assert set(prof) == {"fft_pass_1", "fft_last_power"} and prof["fft_pass_1"][1] == 1, prof
+    ctx.profile_enable(False)
+    mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx)
+    assert ctx.profile_read() == {}
+    ctx.close()
