@@ -348,7 +348,10 @@ int mils_server_take(mils_server *srv, uint64_t ticket, double *power, mils_requ
 int mils_server_stats(mils_server *srv, mils_server_counters *out);
 /* Message of the first device error that stopped a lane ("" if none).  Once
  * every lane has stopped, pending requests complete with MILS_ERR_DEVICE and
- * submit returns MILS_ERR_DEVICE. */
+ * submit returns MILS_ERR_DEVICE.  For tests of this handling, the
+ * environment variable MILS_SERVER_FAIL_AFTER=N (read by mils_server_create)
+ * makes each lane report a device error once it has run N batches, without
+ * touching the device. */
 const char *mils_server_last_error(mils_server *srv);
 /* Stop the lanes; requests not yet done are cancelled (their tickets become
  * invalid).  Waits for batches already on the device. */

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -67,6 +68,8 @@ struct Lane {
   double* d_out = nullptr;
   size_t d_out_cap = 0;
   bool dead = false;
+  bool injected = false;  // stopped by the fault-injection switch
+  int64_t runs = 0;       // batches run
   std::thread th;
 };
 
@@ -113,6 +116,11 @@ struct mils_server {
   uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0;
   uint64_t failed = 0, dead_lanes = 0;
   std::string lane_error;  // message of the first device error that ended a lane
+  // Fault injection for tests of the lane-failure handling: with
+  // MILS_SERVER_FAIL_AFTER=N in the environment when the server is created,
+  // each lane reports a device error once it has run N batches (the batch
+  // that trips it is reported failed; the device is not touched).  -1: off.
+  int64_t fail_after = -1;
   std::vector<double> lat_ms;
   double first_submit = -1.0, last_done = 0.0, sums_done = 0.0;
   std::vector<std::unique_ptr<Lane>> lanes;
@@ -226,7 +234,9 @@ void mils_server::lane_died(Lane* L) {
   ++dead_lanes;
   if (lane_error.empty()) {
     const char* m = mils_last_error(L->ctx);
-    lane_error = (m && m[0]) ? m : "device error";
+    lane_error = L->injected ? "injected lane failure (MILS_SERVER_FAIL_AFTER)"
+                 : (m && m[0]) ? m
+                               : "device error";
   }
   if (dead_lanes < lanes.size()) return;
   const double t = now();
@@ -306,6 +316,10 @@ void mils_server::lane_loop(Lane* L) {
     lk.unlock();
     if (single) run_single(L, batch[0]);
     else run_batch(L, batch);
+    if (fail_after >= 0 && ++L->runs > fail_after) {
+      for (Request* r : batch) r->status = MILS_ERR_DEVICE;
+      L->dead = L->injected = true;
+    }
     lk.lock();
     const double t_done = now();
     inflight -= need;
@@ -345,6 +359,7 @@ int mils_server_create(int device, const mils_server_config* cfg, mils_server** 
   if (!s) return MILS_ERR_OOM;
   s->device = device;
   s->cfg = c;
+  if (const char* e = std::getenv("MILS_SERVER_FAIL_AFTER")) s->fail_after = std::atoll(e);
   s->t0 = Clock::now();
   if (hipSetDevice(device) != hipSuccess) return MILS_ERR_DEVICE;
   (void)hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, device);

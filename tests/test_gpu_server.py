@@ -150,6 +150,39 @@ def test_repeated_large_requests_beside_batches():
     srv.close()
 
 
+def test_lanes_stopped_by_device_errors(monkeypatch):
+    """Lane failure handling, forced from the host: with
+    MILS_SERVER_FAIL_AFTER=1 each lane reports a device error after its first
+    batch (the device is not touched).  The failing batches' requests and
+    those still pending end with MILS_ERR_DEVICE instead of waiting forever,
+    the counters say so, and submit refuses work once no lane is left."""
+    monkeypatch.setenv("MILS_SERVER_FAIL_AFTER", "1")
+    srv = mils.Server(0, lanes=2, max_batch=4)
+    monkeypatch.delenv("MILS_SERVER_FAIL_AFTER")
+    rng = np.random.default_rng(7)
+    cs = [workloads.batch_curve(rng, 500) for _ in range(40)]
+    tks, refused = [], 0
+    for c in cs:  # all submitted before any wait: most are still pending when the lanes stop
+        rc, tk = srv.submit(c.t, c.y, c.dy, c.f0, c.df, c.nf, eps=EPS["fp64"])
+        if rc == mils.MILS_ERR_DEVICE:  # both lanes already stopped
+            refused += 1
+            continue
+        assert rc == mils.MILS_OK, rc
+        tks.append((tk, c))
+    sts = [result(srv, tk, c.nf)[0] for tk, c in tks]
+    assert set(sts) <= {mils.MILS_OK, mils.MILS_ERR_DEVICE}
+    assert sts.count(mils.MILS_OK) <= 2 * 4  # one good batch per lane at most
+    s = srv.stats()
+    print(f"[server fault injection] ok {sts.count(mils.MILS_OK)}, failed "
+          f"{sts.count(mils.MILS_ERR_DEVICE)}, refused {refused}; {srv.last_error()}", flush=True)
+    assert s["dead_lanes"] == 2 and s["failed"] == sts.count(mils.MILS_ERR_DEVICE)
+    assert s["completed"] == s["submitted"] == len(sts)
+    assert "MILS_SERVER_FAIL_AFTER" in srv.last_error()
+    c = cs[0]
+    assert srv.submit(c.t, c.y, c.dy, c.f0, c.df, c.nf)[0] == mils.MILS_ERR_DEVICE
+    srv.close()
+
+
 def test_shutdown_with_requests_in_flight():
     rng = np.random.default_rng(3)
     srv = mils.Server(0, lanes=1)
