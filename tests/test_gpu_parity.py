@@ -6,7 +6,7 @@ compares with the oracle element by element:
   FP64 at eps=1e-9: max|P - P_ref| / max|P_ref| <= 1e-8
   FP32 at eps=1e-5: max|P - P_ref| / max|P_ref| <= 1e-4
   raw sums:         max|g - g_ref| <= 10 eps sum_j |h_j|
-(the tolerances of the NUFFT Lomb-Scargle path; sums are judged in the norm
+(the tolerances of the NUFFT Lomb-Scargle path; sums are compared in the norm
 in which the NUFFT tolerance is defined).
 """
 import numpy as np
