@@ -8,6 +8,7 @@ if libmils.so is missing or cannot be loaded, every call raises.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -331,6 +332,48 @@ def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization=
 def context_status(ctx=None) -> int:
     ctx = ctx or default_context()
     return load().mils_context_status(ctx.handle)
+
+
+def autofrequency(t, samples_per_peak=5.0, nyquist_factor=5.0, minimum_frequency=None,
+                  maximum_frequency=None):
+    """(f0, df, nf) of the automatic frequency grid the paper's benchmarks use
+    (Sec. 3: the Astropy default, N_f ~ 12 N_d).  With T the time baseline
+    (max t - min t) and N the number of points: the step resolves a peak of
+    width 1/T with samples_per_peak frequencies, df = 1 / (samples_per_peak T);
+    the grid starts at minimum_frequency (default df / 2) and ends at the
+    frequency nearest maximum_frequency on the grid (default nyquist_factor
+    times the average Nyquist frequency N / (2 T)).  t: host array or tensor
+    (only its extent and length are read)."""
+    if hasattr(t, "detach"):
+        n = int(t.numel())
+        lo, hi = (float(t.min()), float(t.max())) if n else (0.0, 0.0)
+    else:
+        import numpy as np
+        t = np.asarray(t, dtype=np.float64)
+        n = int(t.size)
+        lo, hi = (float(t.min()), float(t.max())) if n else (0.0, 0.0)
+    T = hi - lo
+    if n < 2 or not (T > 0.0) or not math.isfinite(T):
+        raise ValueError("autofrequency needs at least two distinct finite times")
+    if not (samples_per_peak > 0 and nyquist_factor > 0):
+        raise ValueError("samples_per_peak and nyquist_factor must be positive")
+    df = 1.0 / (samples_per_peak * T)
+    f0 = 0.5 * df if minimum_frequency is None else float(minimum_frequency)
+    fmax = nyquist_factor * 0.5 * n / T if maximum_frequency is None else float(maximum_frequency)
+    if not fmax >= f0:
+        raise ValueError("maximum_frequency below minimum_frequency")
+    nf = 1 + int(round((fmax - f0) / df))
+    return f0, df, nf
+
+
+def lomb_scargle(t, y, dy=None, samples_per_peak=5.0, nyquist_factor=5.0,
+                 minimum_frequency=None, maximum_frequency=None, **kw):
+    """The periodogram on the automatic grid of autofrequency: returns
+    (f0, df, power), power[k] at f0 + k df (float64 device tensor); kw are
+    those of periodogram (eps, precision, normalization, ...)."""
+    f0, df, nf = autofrequency(t, samples_per_peak, nyquist_factor, minimum_frequency,
+                               maximum_frequency)
+    return f0, df, periodogram(t, y, dy, f0, df, nf, **kw)
 
 
 def trig_sums(t, h, f0, df, nf, eps=1e-9, precision="fp64", stream=None, ctx=None):

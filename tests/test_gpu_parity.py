@@ -490,3 +490,20 @@ def test_stage_profiling():
     mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx)
     assert ctx.profile_read() == {}
     ctx.close()
+
+
+# ---------------------------------------------------------------- automatic grid
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lomb_scargle_on_the_automatic_grid(precision):
+    """The periodogram on the automatic frequency grid (N_f ~ 12 N_d) from
+    device tensors, against the oracle at every frequency."""
+    c = workloads.single_small(seed=0)
+    f0, df, p = mils.lomb_scargle(dev(c.t), dev(c.y), dev(c.dy), eps=EPS[precision],
+                                  precision=precision)
+    g0, gd, nf = mils.autofrequency(c.t)
+    assert (f0, df) == (g0, gd) and p.numel() == nf
+    ref = oracle.periodogram(c.t, c.y, c.dy, f0, df, nf=nf)
+    err = rel_err(p.cpu().numpy(), ref)
+    print(f"[lomb_scargle {precision}] N_f = {nf} for N_d = {c.nd}, max-normalised {err:.3e}",
+          flush=True)
+    assert err <= TOL[precision]
