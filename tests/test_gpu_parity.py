@@ -507,3 +507,35 @@ def test_lomb_scargle_on_the_automatic_grid(precision):
     print(f"[lomb_scargle {precision}] N_f = {nf} for N_d = {c.nd}, max-normalised {err:.3e}",
           flush=True)
     assert err <= TOL[precision]
+
+
+# ---------------------------------------------------------------- caller's graph
+def test_call_captured_in_the_callers_graph():
+    """A caller may capture an asynchronous periodogram in a graph of its own
+    (the fork to the second stream and the join are events, so they become
+    graph edges; the context's own replay is bypassed on a capturing stream).
+    Every replay, with eager work and synchronisations between them, gives
+    the eager result."""
+    c = workloads.single_large(seed=3, nd=120_000, span_years=3)  # three passes
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    ctx = mils.Context(0)
+    eager = mils.periodogram(t, y, dy, c.f0, c.df, c.nf, ctx=ctx).cpu().numpy()  # plan, workspace
+    out = torch.empty(c.nf, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        mils.periodogram(t, y, dy, c.f0, c.df, c.nf, out=out, ctx=ctx, sync=False,
+                         stream=torch.cuda.current_stream())
+    for i in range(4):
+        out.zero_()
+        scratch = torch.randn(1 << 20, device="cuda") * 2.0  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        r = out.cpu().numpy()
+        assert np.max(np.abs(r - eager)) <= 1e-13 * np.max(np.abs(eager)), i
+        del scratch
+    assert mils.context_status(ctx) == mils.MILS_OK
+    del g
+    ctx.close()
