@@ -1141,6 +1141,7 @@ int autotune_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
   std::map<int, std::vector<int64_t>> bands;
   for (int64_t c = 0; c < ncurves; ++c) bands[nf_band(nf_off[c + 1] - nf_off[c])].push_back(c);
   std::vector<std::pair<double, int>> cand;
+  // 0: the planner's sigma (1.25 in FP64, 1.5 for batched FP32 series)
   for (double sg : prec == 1 ? std::vector<double>{0.0, 2.0} : std::vector<double>{0.0, 1.5, 2.0})
     for (int tm : {1024, 256}) cand.push_back({sg, tm});
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -23,7 +23,7 @@ struct PlanRequest {
   int tile_max = 0;     // largest spreading tile (cells), 0 = kTileMax
 };
 
-// Default upsampling factor of a precision.
+// Default upsampling factor of a precision (1.25 in both).
 double default_sigma(int prec);
 
 // Kernel width for tolerance eps at upsampling sigma (clamped to [2, 20]).

@@ -119,7 +119,7 @@ def _smooth(n):
 def test_planner_invariants(nf, eps, prec):
     d = mils.plan_info(nd=1000, nf=nf, eps=eps, precision=prec)
     n = d["n"]
-    assert n >= math.ceil((1.25 if prec == "fp64" else 1.5) * nf) - 1
+    assert n >= math.ceil(1.25 * nf) - 1  # sigma 1.25 in both precisions
     assert _smooth(n)
     assert math.prod(d["len"]) == n
     assert 1 <= d["npass"] <= 4

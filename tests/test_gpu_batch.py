@@ -130,7 +130,7 @@ def test_autotuner_decides_per_band_and_keeps_parity(precision):
         torch.cuda.synchronize()
         assert np.all(st == 0)
         dec = ctx.batch_tuning(curves[0].nf, EPS[precision], precision)
-        sigmas = (0.0, 1.5, 2.0) if precision == "fp64" else (0.0, 2.0)
+        sigmas = (0.0, 1.5, 2.0) if precision == "fp64" else (0.0, 2.0)  # 0.0: the planner's
         assert dec is not None and dec[0] in sigmas and dec[1] in (1024, 256), dec
         powers = mils.split_power(out, nf_off)
         worst = 0.0

@@ -65,9 +65,9 @@ def test_every_series_matches_oracle(precision, dy_mode):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_three_pass_plan_sampled(precision):
-    # nf = 4e5 plans three FFT passes in both precisions: the shared B, B2
+    # nf = 6e5 plans three FFT passes in both precisions: the shared B, B2
     # grids and each series' A grid go through the second grid set
-    s = workloads.shared_times(seed=52, nd=2000, nseries=3, span_years=3, nf=400_000)
+    s = workloads.shared_times(seed=52, nd=2000, nseries=3, span_years=3, nf=600_000)
     assert len(mils.plan_info(s.nd, s.nf, EPS[precision], precision, s.f0, s.df)["len"]) == 3
     p = run(s, precision, "shared")
     rng = np.random.default_rng(7)
