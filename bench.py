@@ -310,7 +310,7 @@ def main():
         if lane_err:
             extra["serving"]["lane_error"] = lane_err
 
-    # the brute-force comparison (Sec. 3.1): every sum term by term in FP64 on
+    # the brute-force comparison (Sec. 2.1): every sum term by term in FP64 on
     # the first 1.2e6 frequencies of the same curve (last of the GPU legs: a
     # second of full FP64 load would slow what follows)
     if not args.no_extra:

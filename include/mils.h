@@ -25,6 +25,8 @@
  *     values, dy <= 0, constant data) happen on the device and are reported
  *     by the synchronous call, or by mils_context_status after an _async call;
  *     the output is then unspecified.
+ *   - Point counts nd are 1 <= nd <= 2^30 (per series in the batched call);
+ *     larger counts return MILS_ERR_INVALID_ARG before any device work.
  *   - No C++ exception crosses this interface.  Every call returns a status
  *     code; mils_last_error gives a human-readable message for the context.
  *   - One context may be used by one host thread at a time.  Calls on one
@@ -151,7 +153,7 @@ int mils_plan_info(mils_context *ctx, int64_t nd, const mils_params *p, mils_pla
 /* The polynomial table the spreading kernel is evaluated from, for the plan of
  * a periodogram with parameters p (host-only; valid on a host-only context).
  * The kernel is the exponential of semicircle phi(z) = exp(beta (sqrt(1 - z^2)
- * - 1)) (Sec. 2 of the paper); at the w cells of a point whose first covered
+ * - 1)) (Sec. 1 of the paper); at the w cells of a point whose first covered
  * cell lies t in [0, 1) cells past the left end of its support, cell k takes
  * phi((k + t) / (w/2) - 1) ~= sum_j coef[j * kmax + k] u^(ncoef - 1 - j),
  * u = 2t - 1.  coef receives ncoef * kmax doubles (caller-owned, at least
@@ -200,7 +202,7 @@ int mils_context_status(mils_context *ctx);
 
 /*
  * Direct evaluation (Sec. 1, Eq. 1 term by term; the brute-force method the
- * paper compares with, Sec. 3.1): the same periodogram as mils_periodogram
+ * paper compares with, Sec. 2.1): the same periodogram as mils_periodogram
  * (same arguments, results and statuses) with every sum accumulated over the
  * points in FP64 for every frequency -- O(nd * nf) work, no transform, no
  * approximation beyond FP64 rounding (p->eps and p->precision are ignored).
@@ -223,7 +225,7 @@ int mils_direct_trig_sums(mils_context *ctx, const double *t, const double *h, i
 
 /*
  * Periodograms of nseries series observed at the same times (the batched
- * mode for series sharing their observation times, Sec. 3.1 of the paper).
+ * mode for series sharing their observation times, Sec. 2.1 of the paper).
  * t: nd doubles; y: nseries x nd doubles, series i at y + i*nd; power:
  * nseries x p->nf doubles, series i at power + i*p->nf (all device arrays).
  * dy is NULL (unit weights), one array of nd doubles shared by every series
@@ -277,7 +279,7 @@ int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd
  * them under a few upsampling factors sigma (0 stands for the planner's own
  * choice; larger sigma: a wider grid with a narrower kernel) and largest
  * spreading tiles, and keeps the fastest for later batches of the context
- * (Sec. 2 of the paper sets the grid and the kernel width from eps; which
+ * (Sec. 1 of the paper sets the grid and the kernel width from eps; which
  * admissible pair is fastest depends on the size).  Returns MILS_OK with
  * *sigma and *tile_max set, or MILS_ERR_INVALID_ARG when the band has no
  * decision.  Setting MILS_AUTOTUNE=0 in the environment turns the tuner off. */

@@ -17,6 +17,7 @@
 #include "../../include/mils.h"
 #include "api_internal.h"
 #include "batch.h"
+#include "index_math.h"
 #include "kernels.h"
 #include "mils_internal.h"
 #include "plan.h"
@@ -186,7 +187,7 @@ int check_params(const mils_params* p) {
 }
 
 int check_nd(int64_t nd) {
-  if (nd < 1 || nd > (int64_t)0x7fffffff) return MILS_ERR_INVALID_ARG;
+  if (nd < 1 || nd > kMaxPoints) return MILS_ERR_INVALID_ARG;
   return MILS_OK;
 }
 

@@ -13,6 +13,7 @@
 
 #include "device_math.h"
 #include "fft_core.h"
+#include "index_math.h"
 #include "kernels.h"
 #include "mils_internal.h"
 #include "path_device.h"
@@ -170,13 +171,9 @@ __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Wo
     }
     if (i <= nb) {
       const int b = (int)i;
-      int lo = 0, hi = nd;  // first j in [0, nd) with bin(j) >= b, else nd
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (point_bin(a.t[mid], tau, a.df, p) < b) lo = mid + 1;
-        else hi = mid;
-      }
-      w.bin_start[b] = lo;
+      // first j in [0, nd) with bin(j) >= b, else nd
+      w.bin_start[b] =
+          lower_bound_idx(nd, b, [&](int j) { return point_bin(a.t[j], tau, a.df, p); });
     }
   }
 }
@@ -326,13 +323,8 @@ __global__ __launch_bounds__(kThreads) void k_det_gather(CallArgs a, Plan p, Wor
     }
     if (q <= nb) {
       // first position whose bin is >= q (nd if none)
-      int lo = 0, hi = nd;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)(w.keys[mid] >> 32) < (int)q) lo = mid + 1;
-        else hi = mid;
-      }
-      w.bin_start[q] = lo;
+      w.bin_start[q] =
+          lower_bound_idx(nd, (int)q, [&](int j) { return (int)(w.keys[j] >> 32); });
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) st->need_sort = 1;  // the spread reads the copies

@@ -337,7 +337,7 @@ def context_status(ctx=None) -> int:
 def autofrequency(t, samples_per_peak=5.0, nyquist_factor=5.0, minimum_frequency=None,
                   maximum_frequency=None):
     """(f0, df, nf) of the automatic frequency grid the paper's benchmarks use
-    (Sec. 3: the Astropy default, N_f ~ 12 N_d).  With T the time baseline
+    (Sec. 2: the Astropy default, N_f ~ 12 N_d).  With T the time baseline
     (max t - min t) and N the number of points: the step resolves a peak of
     width 1/T with samples_per_peak frequencies, df = 1 / (samples_per_peak T);
     the grid starts at minimum_frequency (default df / 2) and ends at the

@@ -1,5 +1,5 @@
 """The automatic frequency grid (host logic): the grid the paper's benchmarks
-use (Sec. 3: the Astropy default, N_f ~ 12 N_d), checked against its
+use (Sec. 2: the Astropy default, N_f ~ 12 N_d), checked against its
 definition -- step 1 / (samples_per_peak * baseline), start at half a step,
 end at nyquist_factor times the average Nyquist frequency N / (2 baseline)."""
 import numpy as np

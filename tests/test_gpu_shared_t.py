@@ -1,5 +1,5 @@
 """GPU parity of the shared-times form (series observed at the same times,
-the batched mode of Sec. 3.1) against the CPU oracle, through the C ABI
+the batched mode of Sec. 2.1) against the CPU oracle, through the C ABI
 (mils_periodogram_shared_t).
 
 With shared weights the path computes the weight-only sums B (f) and B2 (2f)
