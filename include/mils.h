@@ -52,7 +52,7 @@ enum {
   MILS_ERR_OOM = -3,         /* device allocation failed or the HBM budget is exceeded */
   MILS_ERR_DEVICE = -4,      /* a HIP runtime error; the context is unusable */
   MILS_ERR_UNSUPPORTED = -5, /* eps outside the range of the precision, size too large */
-  MILS_ERR_BUSY = -6,        /* server queue full */
+  MILS_ERR_BUSY = -6,        /* server queue full; a captured call that would have to allocate */
   MILS_ERR_CANCELLED = -7,   /* server request cancelled (server shut down) */
   MILS_ERR_TIMEOUT = -8      /* server wait timed out */
 };
@@ -183,15 +183,32 @@ int mils_trig_sums(mils_context *ctx, const double *t, const double *h, int64_t 
  * t, y: nd doubles (device); dy: nd doubles (device) or NULL for unit weights;
  * power: p->nf doubles (device), written with the power at f0 + k df.
  * The power is exactly 0 where fl(f0 + fl(k df)) == 0.  Where the fit is
- * singular (e.g. evenly spaced t at a multiple of the Nyquist frequency) the
- * power is 0.  Synchronous: returns after the result is complete, with the
- * status of the device-side content checks.
+ * ill-posed the power is NaN: the determinant D = CC SS - CS^2 of the 2x2
+ * fit (sums normalised by the total weight, after the floating-mean
+ * correction) is at most p->eps (below the accuracy of the transformed sums)
+ * or at most 1e-12 CC SS -- e.g. evenly spaced t at a multiple of the
+ * Nyquist frequency.  mils_context_illposed then counts those frequencies.
+ * Synchronous: returns after the result is complete, with the status of the
+ * device-side content checks.
  */
 int mils_periodogram(mils_context *ctx, const double *t, const double *y, const double *dy,
                      int64_t nd, const mils_params *p, double *power, void *hip_stream);
 
 /* As mils_periodogram, but returns once the work is enqueued on hip_stream.
- * The device-side status is read by mils_context_status. */
+ * The device-side status is read by mils_context_status.
+ *
+ * Graph capture: the call may be captured into the caller's graph on
+ * hip_stream once an uncaptured call with the same nf, eps, precision and an
+ * nd at least as large has run on the context (its plan tables and workspace
+ * then exist).  Otherwise it returns MILS_ERR_BUSY (allocation, upload and
+ * the plan's setup kernel cannot run inside a capture); the context stays
+ * usable.  The graph holds pointers to the context's workspace and plan:
+ * its replays use them as a call would (they must not overlap other calls on
+ * the context), and a later workspace growth keeps the captured buffer
+ * allocated until mils_context_destroy.  The synchronous calls, the
+ * batched, shared-times and direct calls refuse a capturing stream
+ * (MILS_ERR_INVALID_ARG for mils_periodogram, MILS_ERR_UNSUPPORTED for the
+ * others). */
 int mils_periodogram_async(mils_context *ctx, const double *t, const double *y,
                            const double *dy, int64_t nd, const mils_params *p, double *power,
                            void *hip_stream);
@@ -199,6 +216,13 @@ int mils_periodogram_async(mils_context *ctx, const double *t, const double *y,
 /* Wait for the last call enqueued on the context and return its device-side
  * status (MILS_OK, MILS_ERR_INVALID_ARG or MILS_ERR_DEGENERATE). */
 int mils_context_status(mils_context *ctx);
+
+/* Number of frequencies whose power was NaN because the fit was ill-posed
+ * (see mils_periodogram), for the last single-series call (mils_periodogram,
+ * mils_periodogram_async, mils_direct_periodogram) whose status has been read
+ * with status MILS_OK; 0 otherwise.  The batched, shared-times and served
+ * forms mark such frequencies with NaN without counting them. */
+int64_t mils_context_illposed(const mils_context *ctx);
 
 /*
  * Direct evaluation (Sec. 1, Eq. 1 term by term; the brute-force method the

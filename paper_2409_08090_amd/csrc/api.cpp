@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <algorithm>
 #include <map>
@@ -123,8 +124,14 @@ struct mils_context {
   size_t plan_bytes = 0;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  // Set once a call has been captured into a caller's graph: that graph
+  // holds pointers into the workspace, so a later growth keeps the old
+  // buffer (freed with the context) instead of freeing it.
+  bool captured = false;
+  std::vector<char*> retired;
   int* host_status = nullptr;  // pinned
   DevStats* last_stats = nullptr;
+  int64_t last_illposed = 0;  // ill-posed frequencies of the last call whose status was read
   hipStream_t last_stream = nullptr;
   bool have_pending = false;
   // per-stage event timing
@@ -184,6 +191,19 @@ int check_params(const mils_params* p) {
   if (p->eps < lo || p->eps > 1e-2) return MILS_ERR_UNSUPPORTED;
   if (!std::isfinite(p->f0 + (double)(p->nf - 1) * p->df)) return MILS_ERR_INVALID_ARG;
   return MILS_OK;
+}
+
+// Whether the caller is capturing `stream` into a graph (a NULL stream is
+// never captured here).  On a query error the answer is "yes", so that the
+// callers refuse rather than risk an allocation inside a capture.
+bool capturing(hipStream_t stream) {
+  if (!stream) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return cs != hipStreamCaptureStatusNone;
 }
 
 int check_nd(int64_t nd) {
@@ -263,6 +283,14 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   return MILS_OK;
 }
 
+// Whether the single-series plan of (nf, eps, prec, G) exists with its device
+// tables (a call may then run without allocating).
+bool plan_ready(mils_context* ctx, int64_t nf, double eps, int prec, int G) {
+  PlanKey key{nf, eps, prec, G, 0, 0};
+  auto it = ctx->plans.find(key);
+  return it != ctx->plans.end() && it->second.tw;
+}
+
 // Size for a buffer that must hold `need` bytes and holds `have`: half
 // again as large as before at least, so that growing requests (a server's
 // mix of sizes) reallocate rarely -- a reallocation waits for the device --
@@ -294,7 +322,8 @@ int ensure_workspace(mils_context* ctx, size_t bytes) {
   if (ctx->ws) {
     hipError_t he = hipDeviceSynchronize();
     if (he != hipSuccess) return hip_fail(ctx, he, "workspace resize");
-    (void)hipFree(ctx->ws);
+    if (ctx->captured) ctx->retired.push_back(ctx->ws);
+    else (void)hipFree(ctx->ws);
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
   }
@@ -413,13 +442,30 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
   const bool pg = (y != nullptr);
   const int G = pg ? 3 : 1;
+  // A call captured into the caller's graph may use only what an earlier
+  // uncaptured call of the same sizes left: the plan's tables and a large
+  // enough workspace (their allocation, upload and the kernel-transform
+  // kernel cannot run inside a capture), and it cannot wait for its result.
+  const bool cap = capturing(stream);
+  if (cap && sync)
+    return fail(ctx, MILS_ERR_INVALID_ARG,
+                "a synchronous call cannot be captured into a graph: use the _async variant");
+  if (cap && !plan_ready(ctx, p->nf, p->eps, p->precision, G))
+    return fail(ctx, MILS_ERR_BUSY,
+                "captured call needs a plan that does not exist yet: make one uncaptured call "
+                "with these sizes first");
   PlanEntry* pe = nullptr;
   int rc = get_plan(ctx, p->nf, p->eps, p->precision, G, &pe, true);
   if (rc != MILS_OK) return rc;
   const Plan& plan = pe->plan;
   const size_t need = layout_work(plan, nd, G, nullptr, nullptr);
+  if (cap && need > ctx->ws_bytes)
+    return fail(ctx, MILS_ERR_BUSY,
+                "captured call needs a larger workspace: make one uncaptured call with these "
+                "sizes first");
   rc = ensure_workspace(ctx, need);
   if (rc != MILS_OK) return rc;
+  if (cap) ctx->captured = true;
   Work w{};
   layout_work(plan, nd, G, ctx->ws, &w);
   w.tw = pe->tw;
@@ -440,6 +486,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.norm = p->normalization;
   a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
   a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.dmin = p->eps;
   a.periodogram = pg ? 1 : 0;
   a.deterministic = (p->flags & MILS_DETERMINISTIC) ? 1 : 0;
   a.power = power;
@@ -531,6 +578,7 @@ int mils_context_destroy(mils_context* ctx) {
     for (auto& kv : ctx->plans)
       if (kv.second.tw) (void)hipFree(reinterpret_cast<char*>(kv.second.inv_phihat));
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (char* r : ctx->retired) (void)hipFree(r);
     free_batch_state(ctx->batch);
     release_single_graph(ctx);
     if (ctx->sg.cap) (void)hipStreamDestroy(ctx->sg.cap);
@@ -650,6 +698,8 @@ static int run_direct(mils_context* ctx, const double* t, const double* y, const
                       const double* h, int64_t nd, const mils_params* p, double* power,
                       double* sums, hipStream_t stream) {
   if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (capturing(stream))
+    return fail(ctx, MILS_ERR_UNSUPPORTED, "direct evaluation is synchronous: it cannot be captured");
   if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
@@ -729,6 +779,9 @@ int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* 
   hipError_t he = hipSetDevice(ctx->device);
   if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (capturing(stream))
+    return fail(ctx, MILS_ERR_UNSUPPORTED,
+                "the shared-times call reads its sort decision back: it cannot be captured");
   PlanEntry* pe = nullptr;
   rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, true);
   if (rc != MILS_OK) return rc;
@@ -765,6 +818,7 @@ int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* 
   a.norm = p->normalization;
   a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
   a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.dmin = p->eps;
   a.periodogram = 1;
   const bool shared_w = (dy == nullptr || dy_stride == 0);
   if (shared_w) {
@@ -1075,6 +1129,7 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     ba.norm = common->normalization;
     ba.center = (common->flags & MILS_CENTER_DATA) ? 1 : 0;
     ba.fit_mean = (common->flags & MILS_FIT_MEAN) ? 1 : 0;
+    ba.dmin = common->eps;
     ba.status = reinterpret_cast<int*>(B.dev + o_st);
     L.prec = prec;
     size_t io = o_items[k];
@@ -1207,6 +1262,9 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
   if (nd_off[0] != 0 || nf_off[0] != 0) return fail(ctx, MILS_ERR_INVALID_ARG, "offsets must start at 0");
   if (common->flags & MILS_DETERMINISTIC)
     return fail(ctx, MILS_ERR_UNSUPPORTED, "MILS_DETERMINISTIC applies to single-series calls");
+  if (capturing(reinterpret_cast<hipStream_t>(hip_stream)))
+    return fail(ctx, MILS_ERR_UNSUPPORTED,
+                "the batched call uploads its layout synchronously: it cannot be captured");
   for (int64_t c = 0; c < ncurves; ++c) {
     mils_params p = *common;
     p.f0 = f0[c];
@@ -1368,16 +1426,21 @@ int mils_profile_read(mils_context* ctx, double* ms_total, int64_t* launches) {
   return MILS_OK;
 }
 
+int64_t mils_context_illposed(const mils_context* ctx) { return ctx ? ctx->last_illposed : 0; }
+
 int mils_context_status(mils_context* ctx) {
   if (!ctx) return MILS_ERR_INVALID_ARG;
   if (ctx->device < 0) return MILS_OK;
   if (!ctx->have_pending) return MILS_OK;
-  hipError_t he = hipMemcpyAsync(ctx->host_status, &ctx->last_stats->status, sizeof(int),
+  static_assert(offsetof(DevStats, nill) == offsetof(DevStats, status) + sizeof(int),
+                "status and count are read together");
+  hipError_t he = hipMemcpyAsync(ctx->host_status, &ctx->last_stats->status, 2 * sizeof(int),
                                  hipMemcpyDeviceToHost, ctx->last_stream);
   if (he == hipSuccess) he = hipStreamSynchronize(ctx->last_stream);
   if (he != hipSuccess) return hip_fail(ctx, he, "status readback");
   ctx->have_pending = false;
-  int st = *ctx->host_status;
+  int st = ctx->host_status[0];
+  ctx->last_illposed = st == 0 ? ctx->host_status[1] : 0;
   if (st == -1) return fail(ctx, MILS_ERR_INVALID_ARG, "non-finite input or dy <= 0");
   if (st == -2) return fail(ctx, MILS_ERR_DEGENERATE, "constant data: zero reference chi^2");
   return MILS_OK;

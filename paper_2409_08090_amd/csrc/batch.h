@@ -42,6 +42,7 @@ struct BatchArgs {
   const double* dy;
   double* power;
   int norm, center, fit_mean;
+  double dmin;  // power NaN where the fit's determinant is at most dmin
   int* status;                       // per series, caller order
 };
 

@@ -93,6 +93,7 @@ __device__ void stats_block(const CallArgs& a, DevStats* st, double* sh /* 5*NT 
     if (sBad[0]) status = -1;
     else if (!(YY > 0.0)) status = -2;
     st->status = status;
+    st->nill = 0;
     st->nlow = 0;
     st->k_lo = 0;
   }
@@ -202,6 +203,7 @@ __device__ __forceinline__ CallArgs curve_args(const BatchArgs& ba, const BatchC
   a.fcl = c.fcl;
   a.kzero = c.kzero;
   a.norm = ba.norm;
+  a.dmin = ba.dmin;
   a.center = ba.center;
   a.fit_mean = ba.fit_mean;
   a.periodogram = 1;

@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, in
     if (r.bad) status = -1;
     else if (a.periodogram && a.y && !(YY > 0.0)) status = -2;
     st->status = status;
+    st->nill = 0;
     st->nlow = 0;
     st->k_lo = 0;
   }
@@ -427,7 +428,8 @@ __global__ __launch_bounds__(NT) void k_fft_last(PassBufs<Real> b, FftPass ps, P
   const int64_t blk = xcd_remap(blockIdx.x, nblk);
   const DevStats st = *stp;
   fft_last_block<Real, G, EMAX, NT, TW2>(blk, b, ps, pl.n, pl.nf, pl.K, a, tw, inv_phihat, st,
-                                         smem, G == 3 ? lowfix : nullptr, kLowParts);
+                                         smem, G == 3 ? lowfix : nullptr, kLowParts,
+                                         const_cast<int*>(&stp->nill));
 }
 
 // The last pass for a group of series sharing their weights (a.nser grids of
@@ -651,8 +653,9 @@ __global__ __launch_bounds__(kDirThreads) void k_direct(CallArgs a, Work w) {
     if (k >= a.nf) break;
     if (a.periodogram) {
       double pw = ls_power(acc[0][f], acc[1][f], acc[2][f], acc[3][f], acc[4][f], acc[5][f], st,
-                           a.norm, a.fit_mean);
+                           a.norm, a.fit_mean, 0.0);
       if (k == a.kzero) pw = 0.0;
+      else if (pw != pw) atomicAdd(&w.stats->nill, 1);
       a.power[k] = pw;
     } else {
       a.sums[2 * k] = acc[0][f];
@@ -860,27 +863,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     if (e == hipSuccess) e = hipStreamWaitEvent(s2, aux->fork, 0);
     if (e != hipSuccess) return e;
   }
-  if (a.periodogram) {
-    mark(kStageLow, 1, s2);
-    enqueue_lowfreq(a, w, s2);
-    mark(kStageLow, 0, s2);
-  }
 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
   const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
   const int nd = (int)a.nd;
-  if (a.periodogram) {
-    mark(kStageSpread2F, 1, s2);
-    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd, w.rowflag_2f,
-                       w.act_rows_2f, 1);
-    if (a.deterministic)
-      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1, true>), dim3(sgrid), dim3(kThreads), 0, s2, a,
-                         p, w, 2, w.act_rows_2f, 1);
-    else
-      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w,
-                         2, w.act_rows_2f, 1);
-    mark(kStageSpread2F, 0, s2);
-  }
+  // The f geometry (row classes, spread and then the first FFT pass of its
+  // two grids) is the longer branch: it is launched (and captured) first.
   mark(kStageSpreadF, 1, s);
   hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
                      w.act_rows_f, 0);
@@ -894,6 +882,23 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
                        w.act_rows_f, 0);
   mark(kStageSpreadF, 0, s);
+  if (a.periodogram) {
+    mark(kStageLow, 1, s2);
+    enqueue_lowfreq(a, w, s2);
+    mark(kStageLow, 0, s2);
+  }
+  if (a.periodogram) {
+    mark(kStageSpread2F, 1, s2);
+    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd, w.rowflag_2f,
+                       w.act_rows_2f, 1);
+    if (a.deterministic)
+      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1, true>), dim3(sgrid), dim3(kThreads), 0, s2, a,
+                         p, w, 2, w.act_rows_2f, 1);
+    else
+      hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w,
+                         2, w.act_rows_2f, 1);
+    mark(kStageSpread2F, 0, s2);
+  }
   // passes 0 .. npass-2; launch over grids [g0, g0 + ng) of the current set
   T2* cur[3];
   T2* alt[3];
@@ -913,12 +918,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   };
   if (p.npass >= 2) {
     if (fork) {
-      mark(kStagePass0, 1, s2);
-      pass(0, 2, 1, s2);  // 2f grid
-      mark(kStagePass0, 0, s2);
       mark(kStagePass0, 1, s);
       pass(0, 0, 2, s);   // f grids
       mark(kStagePass0, 0, s);
+      mark(kStagePass0, 1, s2);
+      pass(0, 2, 1, s2);  // 2f grid
+      mark(kStagePass0, 0, s2);
     } else {
       mark(kStagePass0, 1, s);
       pass(0, 0, G, s);

@@ -76,6 +76,7 @@ struct DevStats {
   int unsorted;    // t not non-decreasing
   int need_sort;   // points must go through the counting sort
   int status;      // 0 ok, -1 invalid input, -2 degenerate (YY == 0)
+  int nill;        // frequencies whose fit is ill-posed (power NaN), counted by the last pass
   int nlow;        // frequencies evaluated directly near f = 0 (see lowfix)
   int64_t k_lo;    // first of them
 };
@@ -93,6 +94,11 @@ struct CallArgs {
   int64_t kzero;      // output index with f == 0 exactly, or -1
   int norm;
   int center, fit_mean;
+  // A fit whose determinant D = CC SS - CS^2 (sums normalised by the total
+  // weight) is at most dmin is ill-posed at the transform's accuracy: its
+  // power is NaN.  dmin = eps for transformed sums; sums evaluated directly
+  // use only the relative test D <= 1e-12 CC SS.
+  double dmin;
   int periodogram;    // 1: three grids + power; 0: one grid + complex sums
   int deterministic;  // fixed summation orders (bitwise-reproducible results)
   double* power;      // periodogram output

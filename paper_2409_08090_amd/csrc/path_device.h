@@ -429,7 +429,7 @@ __device__ void fft_pass_block(int64_t blk, const typename cplx<Real>::T* in,
 // identities; the 2x2 fit is solved in closed form (tau-free form).
 __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, double Bi, double B2r,
                                            double B2i, const DevStats& st, int norm,
-                                           int fit_mean) {
+                                           int fit_mean, double dmin) {
   double CC = 0.5 * (1.0 + B2r);
   double SS = 0.5 * (1.0 - B2r);
   double CS = 0.5 * B2i;
@@ -442,7 +442,8 @@ __device__ __forceinline__ double ls_power(double Ar, double Ai, double Br, doub
     YS -= st.Ybar * Bi;
   }
   const double D = CC * SS - CS * CS;
-  if (!(D > 0.0)) return 0.0;
+  // ill-posed: D below the accuracy of the sums, or below 1e-12 of CC SS
+  if (!(D > dmin) || !(D > 1e-12 * CC * SS)) return __builtin_nan("");
   const double N = SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS;
   const double YYD = st.YY * D;
   switch (norm) {
@@ -475,7 +476,8 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
                                int64_t n, int64_t nf, int64_t K, const CallArgs& a,
                                const typename cplx<Real>::T* tw, const double* inv_phihat,
                                const DevStats& st, unsigned char* smem,
-                               const double* lowfix = nullptr, int lowparts = 1) {
+                               const double* lowfix = nullptr, int lowparts = 1,
+                               int* nill = nullptr) {
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
   const int L = ps.L, D = ps.C;
@@ -565,13 +567,15 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
         const T2 A = buf[k * R + g * D + d];
         double s6[6] = {(double)A.x * ip, (double)A.y * ip, B.x, B.y, B2.x, B2.y};
         const int64_t q = kout - sg.k_lo;
-        if (q >= 0 && q < sg.nlow) {
+        const bool low = q >= 0 && q < sg.nlow;
+        if (low) {
           const double* lf = a.slow[g];
           for (int j = 0; j < 6; ++j) s6[j] = lf[6 * q + j];
           for (int r = 1; r < lowparts; ++r)
             for (int j = 0; j < 6; ++j) s6[j] += lf[r * 6 * kLowMax + 6 * q + j];
         }
-        double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], sg, a.norm, a.fit_mean);
+        double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], sg, a.norm, a.fit_mean,
+                             low ? 0.0 : a.dmin);
         if (kout == a.kzero) pw = 0.0;
         a.spow[g][kout] = pw;
       }
@@ -582,13 +586,16 @@ __device__ void fft_last_block(int64_t blk, const PassBufs<Real>& b, const FftPa
       double s6[6] = {(double)A.x * ip,  (double)A.y * ip,  (double)B.x * ip,
                       (double)B.y * ip,  (double)B2.x * ip, (double)B2.y * ip};
       const int64_t q = kout - st.k_lo;
-      if (lowfix && q >= 0 && q < st.nlow) {
+      const bool low = lowfix && q >= 0 && q < st.nlow;
+      if (low) {
         for (int j = 0; j < 6; ++j) s6[j] = lowfix[6 * q + j];
         for (int r = 1; r < lowparts; ++r)
           for (int j = 0; j < 6; ++j) s6[j] += lowfix[r * 6 * kLowMax + 6 * q + j];
       }
-      double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean);
+      double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean,
+                           low ? 0.0 : a.dmin);
       if (kout == a.kzero) pw = 0.0;
+      else if (nill && pw != pw) atomicAdd(nill, 1);
       a.power[kout] = pw;
     } else {
       const T2 A = buf[k * R + d];

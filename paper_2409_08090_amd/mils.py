@@ -112,6 +112,7 @@ SIGNATURES = {
     "mils_periodogram_async": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params),
                                 _P, _P], ctypes.c_int),
     "mils_context_status": ([_P], ctypes.c_int),
+    "mils_context_illposed": ([_P], ctypes.c_int64),
     "mils_periodogram_batch": ([_P, ctypes.c_int64, _I64P, _P, _P, _P, _I64P, _D, _D,
                                 ctypes.POINTER(mils_params), _P,
                                 ctypes.POINTER(ctypes.c_int32), _P], ctypes.c_int),
@@ -327,6 +328,13 @@ def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization=
             ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     ctx.check(rc)
     return out
+
+
+def context_illposed(ctx=None) -> int:
+    """Frequencies whose power was NaN (ill-posed fit) in the context's last
+    single-series call whose status has been read."""
+    ctx = ctx or default_context()
+    return int(load().mils_context_illposed(ctx.handle))
 
 
 def context_status(ctx=None) -> int:

@@ -539,3 +539,34 @@ def test_call_captured_in_the_callers_graph():
     assert mils.context_status(ctx) == mils.MILS_OK
     del g
     ctx.close()
+
+
+# ---------------------------------------------------------------- ill-posed frequencies
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_illposed_frequencies_are_nan_and_counted(precision):
+    """Evenly spaced times t_j = j/64 with unit weights: at f = 32, 64, 96
+    (multiples of the Nyquist frequency) the sine column vanishes or the cosine
+    column is constant, so the fit is singular.  The oracle flags those
+    frequencies (Cholesky pivot below 1e-12 of its diagonal) and returns NaN;
+    the library returns NaN there too and counts them, and matches the oracle
+    at every other frequency."""
+    nd = 64
+    t = np.arange(nd) / nd
+    y = np.random.default_rng(11).normal(0.0, 1.0, nd)
+    f0 = df = 0.5
+    nf = 220  # f = 0.5 .. 110
+    ctx = mils.Context(0)
+    p = mils.periodogram(dev(t), dev(y), None, f0, df, nf, eps=EPS[precision],
+                         precision=precision, ctx=ctx).cpu().numpy()
+    ref, flags = oracle.periodogram(t, y, None, f0, df, nf=nf, return_flags=True)
+    bad_ref = flags == 2
+    assert set(np.flatnonzero(bad_ref)) >= {63, 127, 191}  # f = 32, 64, 96
+    np.testing.assert_array_equal(np.isnan(p), bad_ref)
+    assert mils.context_illposed(ctx) == int(bad_ref.sum())
+    ok = ~bad_ref
+    assert rel_err(p[ok], ref[ok]) <= TOL[precision]
+    # a well-posed call resets the count
+    c = workloads.single_small(seed=0)
+    mils.periodogram(dev(c.t), dev(c.y), dev(c.dy), c.f0, c.df, c.nf, ctx=ctx)
+    assert mils.context_illposed(ctx) == 0
+    ctx.close()
