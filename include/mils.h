@@ -113,6 +113,7 @@ typedef struct {
   int32_t first_cols;  /* columns per workgroup of the first pass (npass > 1) */
   int32_t first_lds_bytes; /* dynamic LDS of one workgroup of the first pass (npass > 1) */
   int32_t big;         /* 1: the passes run as 1024-thread workgroups with up to 160 KB LDS */
+  int32_t fft2;        /* 1: two-pass register-tile FFT, n = len[0] * len[1] (single-series calls) */
 } mils_plan_desc;
 
 /* Library version (MILS_VERSION of the build). */
@@ -145,6 +146,14 @@ int mils_context_destroy(mils_context *ctx);
  * a replay saves.  Disabling releases the context's graph (after its last
  * replay has finished). */
 int mils_context_set_graphs(mils_context *ctx, int enable);
+
+/* Whether the context's single-series calls (mils_periodogram, _async,
+ * mils_trig_sums) may use the two-pass register-tile FFT for grids that
+ * would otherwise need three or more passes (Sec. 1: the FFT of the
+ * upsampled grid; see mils_plan_desc.fft2).  On by default, off when the
+ * environment has MILS_FFT2=0 at context creation; the plans of both
+ * choices are cached side by side. */
+int mils_context_set_fft2(mils_context *ctx, int enable);
 
 /* Fill *out with the plan for a periodogram of nd points with parameters p.
  * Host-only; valid on a host-only context. */

@@ -18,6 +18,7 @@
 #include "../../include/mils.h"
 #include "api_internal.h"
 #include "batch.h"
+#include "fft2.h"
 #include "index_math.h"
 #include "kernels.h"
 #include "mils_internal.h"
@@ -31,6 +32,7 @@ struct PlanEntry {
   Plan plan;
   void* tw = nullptr;            // twiddles (FP64 or FP32 pairs)
   double* inv_phihat = nullptr;  // K + 1 doubles
+  double* inv_phihat2 = nullptr; // two-pass plans: n doubles in last-pass order
   size_t bytes = 0;
 };
 
@@ -129,6 +131,9 @@ struct mils_context {
   // buffer (freed with the context) instead of freeing it.
   bool captured = false;
   std::vector<char*> retired;
+  // single-series calls may use the two-pass register-tile FFT (plans keyed
+  // by this choice, so both kinds can coexist in the cache)
+  bool fft2 = true;
   int* host_status = nullptr;  // pinned
   DevStats* last_stats = nullptr;
   int64_t last_illposed = 0;  // ill-posed frequencies of the last call whose status was read
@@ -143,7 +148,7 @@ struct mils_context {
   int num_cu = 256;
   // second stream (default priority) and fork/join events of a periodogram
   hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_mid = nullptr;
   BatchState batch;
   // the single-series call captured as a HIP graph: its key (arguments,
   // workspace layout, plan) was seen on the previous call; replayed while
@@ -211,9 +216,20 @@ int check_nd(int64_t nd) {
   return MILS_OK;
 }
 
+// The two-pass register-tile FFT for single-series calls (MILS_FFT2=0 turns
+// it off: those plans then use three or more LDS passes).
+bool fft2_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("MILS_FFT2");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEntry** out,
-             bool upload, bool batch = false, int64_t n_fixed = 0, int tile_max = 0) {
-  PlanKey key{nf, eps, prec, G + (batch ? 10 : 0), n_fixed, tile_max};
+             bool upload, bool batch = false, int64_t n_fixed = 0, int tile_max = 0,
+             bool fft2 = false) {
+  PlanKey key{nf, eps, prec, G + (batch ? 10 : 0) + (fft2 ? 20 : 0), n_fixed, tile_max};
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end() && (!upload || it->second.tw)) {
     *out = &it->second;
@@ -225,6 +241,7 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   r.batch = batch;
   r.n_fixed = n_fixed;
   r.tile_max = tile_max;
+  r.fft2 = fft2;
   if (!make_plan(r, &e.plan, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
   std::vector<double> tw;
   make_twiddles(&e.plan, &tw);
@@ -237,11 +254,12 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
     std::vector<double> hc;
     make_horner(e.plan, &hc);
     const size_t hbytes = hc.size() * (prec == 1 ? sizeof(float) : sizeof(double));
-    e.bytes = twbytes + phbytes + nbytes + hbytes;
+    const size_t p2bytes = e.plan.fft2 ? sizeof(double) * e.plan.n : 0;
+    e.bytes = twbytes + phbytes + nbytes + hbytes + p2bytes;
     if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + e.bytes > ctx->budget)
       return fail(ctx, MILS_ERR_OOM, "plan tables exceed the HBM budget");
     char* buf = nullptr;
-    hipError_t he = hipMalloc(&buf, twbytes + phbytes + nbytes + hbytes + 1024);
+    hipError_t he = hipMalloc(&buf, twbytes + phbytes + nbytes + hbytes + p2bytes + 1280);
     if (he != hipSuccess) return fail(ctx, MILS_ERR_OOM, "hipMalloc of plan tables failed");
     e.inv_phihat = reinterpret_cast<double*>(buf);
     e.tw = buf + ((phbytes + 255) & ~(size_t)255);
@@ -267,8 +285,13 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
     }
     if (he != hipSuccess) return hip_fail(ctx, he, "plan upload");
     e.plan.hcoef = hdev;
+    if (e.plan.fft2)
+      e.inv_phihat2 = reinterpret_cast<double*>(hdev + ((hbytes + 255) & ~(size_t)255));
     he = launch_phihat(e.inv_phihat, e.plan.K, (double)e.plan.w, (double)e.plan.n, nodes,
                        nodes + z.size(), (int)z.size(), nullptr);
+    if (he == hipSuccess && e.plan.fft2)
+      he = launch_phihat2(e.inv_phihat2, e.inv_phihat, e.plan.pass[0].L, e.plan.pass[1].L,
+                          e.plan.n, e.plan.nf, e.plan.K, nullptr);
     if (he == hipSuccess) he = hipDeviceSynchronize();
     if (he != hipSuccess) return hip_fail(ctx, he, "phihat kernel");
     ctx->plan_bytes += e.bytes;
@@ -286,7 +309,7 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
 // Whether the single-series plan of (nf, eps, prec, G) exists with its device
 // tables (a call may then run without allocating).
 bool plan_ready(mils_context* ctx, int64_t nf, double eps, int prec, int G) {
-  PlanKey key{nf, eps, prec, G, 0, 0};
+  PlanKey key{nf, eps, prec, G + (ctx->fft2 ? 20 : 0), 0, 0};
   auto it = ctx->plans.find(key);
   return it != ctx->plans.end() && it->second.tw;
 }
@@ -455,7 +478,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
                 "captured call needs a plan that does not exist yet: make one uncaptured call "
                 "with these sizes first");
   PlanEntry* pe = nullptr;
-  int rc = get_plan(ctx, p->nf, p->eps, p->precision, G, &pe, true);
+  int rc = get_plan(ctx, p->nf, p->eps, p->precision, G, &pe, true, false, 0, 0, ctx->fft2);
   if (rc != MILS_OK) return rc;
   const Plan& plan = pe->plan;
   const size_t need = layout_work(plan, nd, G, nullptr, nullptr);
@@ -470,6 +493,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   layout_work(plan, nd, G, ctx->ws, &w);
   w.tw = pe->tw;
   w.inv_phihat = pe->inv_phihat;
+  w.inv_phihat2 = pe->inv_phihat2;
 
   CallArgs a;
   std::memset(&a, 0, sizeof(a));  // the bytes serve as a graph key
@@ -492,7 +516,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   a.power = power;
   a.sums = sums;
   StageHook hook{prof_hook, ctx};
-  AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
+  AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join, ctx->ev_mid};
   if (!ctx->prof && ctx->aux && ctx->sg.enabled && graphs_enabled()) {
     he = launch_single_graph(ctx, a, plan, w, stream, aux);
   } else {
@@ -543,6 +567,7 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
   if (!c) return MILS_ERR_OOM;
   c->device = device;
   c->budget = hbm_budget_bytes;
+  c->fft2 = fft2_enabled();
   if (device >= 0) {
     int count = 0;
     hipError_t he = hipGetDeviceCount(&count);
@@ -559,6 +584,7 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming);
     if (he != hipSuccess) {
       std::lock_guard<std::mutex> lk(g_err_mu);
       g_create_err = std::string("context init: ") + hipGetErrorString(he);
@@ -585,6 +611,7 @@ int mils_context_destroy(mils_context* ctx) {
     if (ctx->sg.done) (void)hipEventDestroy(ctx->sg.done);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->ev_mid) (void)hipEventDestroy(ctx->ev_mid);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     if (ctx->host_status) (void)hipHostFree(ctx->host_status);
     for (auto& r : ctx->prof_recs) {
@@ -611,7 +638,7 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
   if (rc == MILS_OK) rc = check_params(p);
   if (rc != MILS_OK) return fail(ctx, rc, "invalid plan query");
   PlanEntry* pe = nullptr;
-  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false);
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false, false, 0, 0, ctx->fft2);
   if (rc != MILS_OK) return rc;
   const Plan& pl = pe->plan;
   std::memset(out, 0, sizeof(*out));
@@ -638,6 +665,14 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
       out->first_cols = fp.C;
       out->first_lds_bytes = (int32_t)(elem * ((size_t)fp.L * fp.C + ntw_f) + fp.L + 16);
     }
+    out->fft2 = pl.fft2;
+    if (pl.fft2) {
+      const bool h = pl.prec == 0;
+      out->first_lds_bytes = (int32_t)(pl.prec == 1 ? f2_first_lds<float>(pl.pass[0].L, pl.pass[0].C, h)
+                                                    : f2_first_lds<double>(pl.pass[0].L, pl.pass[0].C, h));
+      out->last_lds_bytes = (int32_t)(pl.prec == 1 ? f2_last_lds<float>(pl.pass[1].L, 3, h)
+                                                   : f2_last_lds<double>(pl.pass[1].L, 3, h));
+    }
   }
   return MILS_OK;
 }
@@ -648,7 +683,7 @@ int mils_kernel_table(mils_context* ctx, const mils_params* p, double* coef, int
   int rc = check_params(p);
   if (rc != MILS_OK) return fail(ctx, rc, "invalid plan query");
   PlanEntry* pe = nullptr;
-  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false);
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false, false, 0, 0, ctx->fft2);
   if (rc != MILS_OK) return rc;
   std::vector<double> hc;
   make_horner(pe->plan, &hc);
@@ -857,7 +892,7 @@ int mils_periodogram_shared_t(mils_context* ctx, const double* t, const double* 
       he = launch_series_group(a, plan, ww, sg, stream);
     }
   } else {
-    AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join};
+    AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join, ctx->ev_mid};
     for (int64_t i = 0; i < nseries && he == hipSuccess; ++i) {
       CallArgs as = a;
       as.y = y + i * nd;
@@ -1381,6 +1416,12 @@ int mils_profile_enable(mils_context* ctx, int enable) {
     ctx->prof_pool.push_back(std::get<2>(r));
   }
   ctx->prof_recs.clear();
+  return MILS_OK;
+}
+
+int mils_context_set_fft2(mils_context* ctx, int enable) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  ctx->fft2 = enable != 0;
   return MILS_OK;
 }
 

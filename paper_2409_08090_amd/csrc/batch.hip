@@ -253,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_bpro(BatchArgs ba) {
 // one flag read.
 template <typename Real, int GEO, int NG>
 __global__ __launch_bounds__(NT) void k_bspread(BatchArgs ba, const BatchItem* items) {
-  __shared__ Real acc[NG * 2 * kTileMax];
+  __shared__ double acc[NG * 2 * kTileMax];
   __shared__ int rb[8], re[8], sv[2];
   __shared__ SpreadRecords<Real, NG, NT> rec;
   __shared__ Plan sp;

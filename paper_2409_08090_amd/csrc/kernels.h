@@ -24,6 +24,7 @@ enum Stage {
 struct AuxStream {
   hipStream_t s;
   hipEvent_t fork, join;
+  hipEvent_t mid;  // two-pass plans: the second branch's spread is done
 };
 
 // Optional hook called before (begin = 1) and after (begin = 0) each stage is
@@ -66,6 +67,10 @@ hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
 // w.stats, which with w.partials is all of w it uses): the power (a.power) or,
 // with a.periodogram == 0, the raw sums of a.h (a.sums, interleaved re/im).
 hipError_t launch_direct(const CallArgs& a, const Work& w, hipStream_t s);
+
+// 1 / phihat in the order of the two-pass FFT's last pass (see k_phihat2).
+hipError_t launch_phihat2(double* iphi2, const double* inv_phihat, int L0, int L1, int64_t n,
+                          int64_t nf, int64_t K, hipStream_t s);
 
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
                          const double* gphi, int q, hipStream_t s);

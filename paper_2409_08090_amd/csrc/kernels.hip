@@ -11,7 +11,12 @@
 //                rescaling), crop to the requested modes and power assembly
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <type_traits>
+
 #include "device_math.h"
+#include "fft2.h"
 #include "fft_core.h"
 #include "index_math.h"
 #include "kernels.h"
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int n
 template <typename Real, int GEO, int NG, bool DET = false>
 __global__ __launch_bounds__(kThreads) void k_spread_rows(CallArgs a, Plan p, Work w, int gbase,
                                                           const int* act_rows, int slot) {
-  __shared__ Real acc[NG * 2 * kTileMax];
+  __shared__ double acc[NG * 2 * kTileMax];
   __shared__ int rb[8], re[8], sv[2];
   __shared__ SpreadRecords<Real, NG, kThreads> rec;
   const DevStats* stp = w.stats;
@@ -545,6 +550,214 @@ __global__ __launch_bounds__(kThreads) void k_phihat(double* inv_phihat, int64_t
   inv_phihat[i] = 1.0 / (w * s);
 }
 
+// 1 / phihat in the order of the two-pass last pass: entry m0 L1 + m1 is the
+// factor of mode m = m0 + L0 m1 (0 where m is cropped).
+__global__ __launch_bounds__(kThreads) void k_phihat2(double* iphi2, const double* inv_phihat,
+                                                      int L0, int L1, int64_t n, int64_t nf,
+                                                      int64_t K) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t m0 = i / L1, m1 = i - m0 * L1;
+  const int64_t k = fft2::crop(m0 + (int64_t)L0 * m1, n, nf, K);
+  double v = 0.0;
+  if (k >= 0) {
+    const int64_t mm = k - K;
+    v = inv_phihat[mm < 0 ? -mm : mm];
+  }
+  iphi2[i] = v;
+}
+
+// ============================================================================
+// Two-pass register-tile FFT (fft2.h).
+// ============================================================================
+// First pass: the C columns s0 .. s0+C-1 of grid blockIdx.y; the rows whose
+// flag is clear are zero and are not read.  Output: the column block stored
+// contiguously, element (s, m0) at (s / C) L0 C + m0 C + s mod C, multiplied
+// by exp(2 pi i s m0 / n).
+template <typename Real, int L0, int C, bool HALVES>
+__global__ __launch_bounds__(C * L0 / 16, 4) void k_fft2_first(Fft2Bufs<Real> b, FftPass ps,
+                                                             const typename cplx<Real>::T* tw,
+                                                             const DevStats* st) {
+  using T2 = typename cplx<Real>::T;
+  using Lds = typename std::conditional<HALVES, Real, T2>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (st->status != 0) return;
+  constexpr int TL = L0 / 16, NT = C * TL, LP = fft2::line_pitch(L0);
+  static_assert(NT <= 1024 && (C & (C - 1)) == 0, "first-pass workgroup shape");
+  const int tid = threadIdx.x;
+  const int c = tid & (C - 1), t = tid / C;
+  const int g = blockIdx.y;
+  const int64_t sb = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  const int64_t L1 = ps.S;
+  const int64_t s = sb * C + c;
+  Lds* ex = reinterpret_cast<Lds*>(smem);
+  T2* twl = reinterpret_cast<T2*>(smem + (size_t)C * LP * sizeof(Lds));
+  unsigned char* rf = reinterpret_cast<unsigned char*>(twl + tw2_count(L0));
+  // row flags (and the twiddle table) first: the loads depend on them
+  for (int x = tid; x < tw2_count(L0); x += NT) twl[x] = tw[ps.twL_off + x];
+  const unsigned char* rfg = b.rowflag[g];
+  for (int x = tid; x < L0; x += NT) rf[x] = rfg[x];
+  __syncthreads();
+  T2 v[16];
+  const T2* in = b.grid[g] + s;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int row = t + q * TL;
+    v[q] = czero<T2>();
+    if (rf[row]) v[q] = in[(int64_t)row * L1];
+  }
+  // inter-pass twiddles exp(2 pi i s m0 / n) of this thread's outputs
+  // m0 = t + TL j: the first and the step from the two-level table, fetched
+  // before the transform so that their latency overlaps it
+  const int64_t mask = ((int64_t)1 << ps.bshift) - 1;
+  const T2* tlo = tw + ps.twlo_off;
+  const T2* thi = tw + ps.twhi_off;
+  const int64_t q0 = s * t, qs = s * TL;
+  const T2 w0 = cmul(thi[q0 >> ps.bshift], tlo[q0 & mask]);
+  const T2 ws = cmul(thi[qs >> ps.bshift], tlo[qs & mask]);
+  f2_line<L0, HALVES>(v, t, ex + c * LP, twl);
+  T2* out = b.mid[g] + sb * (int64_t)(L0 * C) + c;
+  T2 tk = w0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    out[(int64_t)(t + TL * j) * C] = cmul(v[f2_reg_of<L0>(j)], tk);
+    tk = cmul(tk, ws);
+  }
+}
+
+// Last pass: row m0 of each of the G grids (threads g * TL + t), read from
+// the column blocks in pieces of C elements.  G = 3: the grid-0 threads take
+// B and B2 of their outputs from the other grids' threads (through LDS) and
+// write the power of mode m = m0 + L0 m1 to out[m0 L1 + m1]; G = 1: the
+// deconvolved sums (double2).  Cropped modes are not written.
+template <typename Real, int L1, int G, int C, bool HALVES>
+__global__ __launch_bounds__(G * L1 / 16, G == 3 ? 3 : 2) void k_fft2_last(Fft2Bufs<Real> b, FftPass ps, Plan pl,
+                                                            CallArgs a,
+                                                            const typename cplx<Real>::T* tw,
+                                                            const double* iphi2,
+                                                            const DevStats* stp,
+                                                            const double* lowfix, void* outv) {
+  using T2 = typename cplx<Real>::T;
+  using Lds = typename std::conditional<HALVES, Real, T2>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (stp->status != 0) return;
+  constexpr int TL = L1 / 16, NT = G * TL, LP = fft2::line_pitch(L1);
+  static_assert(NT <= 1024, "last-pass workgroup shape");
+  const int tid = threadIdx.x;
+  const int g = tid / TL, t = tid - g * TL;
+  const int64_t L0 = ps.P;
+  const int64_t m0 = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  // power (G = 3): the grids' results gathered in LDS, all of them (FP32) or
+  // half the outputs at a time (FP64), and the power of each output computed
+  // by one of all the workgroup's threads
+  constexpr int NR = (G == 3 && HALVES) ? 2 : 1;  // rounds over the outputs
+  constexpr int MR = L1 / NR;                      // outputs per round
+  constexpr int PPT = (MR + NT - 1) / NT;          // outputs per thread and round
+  const size_t exb = (size_t)G * LP * sizeof(Lds);
+  const size_t cbb = G == 3 ? (size_t)G * MR * sizeof(T2) : 0;
+  Lds* ex = reinterpret_cast<Lds*>(smem);
+  T2* twl = reinterpret_cast<T2*>(smem + (exb > cbb ? exb : cbb));
+  T2 v[16];
+  const T2* in = b.mid[g] + m0 * C;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int sc = t + q * TL;
+    v[q] = in[(int64_t)(sc / C) * (L0 * C) + (sc & (C - 1))];
+  }
+  // the kernel-transform factors of the outputs this thread finishes
+  constexpr int NIP = G == 3 ? NR * PPT : 16;
+  double ipv[NIP];
+  {
+    const double* ip = iphi2 + m0 * L1;
+#pragma unroll
+    for (int i = 0; i < NIP; ++i) {
+      int m1;
+      if constexpr (G == 3) m1 = (i / PPT) * MR + tid + NT * (i % PPT);
+      else m1 = t + TL * i;
+      ipv[i] = (G != 3 || (tid + NT * (i % PPT)) < MR) ? ip[m1] : 0.0;
+    }
+  }
+  for (int x = tid; x < tw2_count(L1); x += NT) twl[x] = tw[ps.twL_off + x];
+  __syncthreads();
+  f2_line<L1, HALVES>(v, t, ex + g * LP, twl);
+  const int64_t n = pl.n, nf = a.nf, K = pl.K;
+  if constexpr (G == 3) {
+    const DevStats st = *stp;
+    T2* cb = reinterpret_cast<T2*>(smem);  // [G][MR]: free once the last stage has read it
+    double* pw = reinterpret_cast<double*>(outv) + m0 * L1;
+    int* nill = const_cast<int*>(&stp->nill);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+#pragma unroll
+      for (int j = r * (16 / NR); j < (r + 1) * (16 / NR); ++j)
+        cb[g * MR + t + TL * j - r * MR] = v[f2_reg_of<L1>(j)];
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const int mm = tid + NT * i;
+        if (mm >= MR) continue;
+        const int64_t m1 = r * MR + mm;
+        const int64_t kout = fft2::crop(m0 + L0 * m1, n, nf, K);
+        if (kout < 0) continue;
+        const double ip = ipv[r * PPT + i];
+        const T2 A = cb[mm], B = cb[MR + mm], B2 = cb[2 * MR + mm];
+        double s6[6] = {(double)A.x * ip, (double)A.y * ip, (double)B.x * ip,
+                        (double)B.y * ip, (double)B2.x * ip, (double)B2.y * ip};
+        const int64_t q = kout - st.k_lo;
+        const bool low = q >= 0 && q < st.nlow;
+        if (low) {
+          for (int c6 = 0; c6 < 6; ++c6) s6[c6] = lowfix[6 * q + c6];
+          for (int pp = 1; pp < kLowParts; ++pp)
+            for (int c6 = 0; c6 < 6; ++c6) s6[c6] += lowfix[pp * 6 * kLowMax + 6 * q + c6];
+        }
+        double p = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean,
+                            low ? 0.0 : a.dmin);
+        if (kout == a.kzero) p = 0.0;
+        else if (p != p) atomicAdd(nill, 1);
+        pw[m1] = p;
+      }
+      if (r + 1 < NR) __syncthreads();
+    }
+  } else {
+    double2* sums = reinterpret_cast<double2*>(outv) + m0 * L1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int64_t m1 = t + TL * j;
+      if (fft2::crop(m0 + L0 * m1, n, nf, K) < 0) continue;
+      const T2 A = v[f2_reg_of<L1>(j)];
+      sums[m1] = make_double2((double)A.x * ipv[j], (double)A.y * ipv[j]);
+    }
+  }
+}
+
+// Results of the last pass, [L0][L1] by (m0, m1), into frequency order:
+// out[crop(m0 + L0 m1)] through TILE x TILE tiles in LDS (rows of the tile
+// read along m1, written along m0, so both sides move whole lines).
+template <typename V, int TILE>
+__global__ __launch_bounds__(256) void k_fft2_out(const V* __restrict__ res, V* __restrict__ out,
+                                                  int L0, int L1, int64_t n, int64_t nf, int64_t K,
+                                                  const DevStats* st) {
+  __shared__ V tile[TILE][TILE + 1];
+  if (st->status != 0) return;
+  constexpr int RS = 256 / TILE;
+  const int64_t bid = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  const int nt1 = L1 / TILE;
+  const int64_t tm1 = bid % nt1, tm0 = bid / nt1;
+  const int tx = threadIdx.x % TILE, ty = threadIdx.x / TILE;
+#pragma unroll
+  for (int r = 0; r < TILE; r += RS) {
+    const int64_t m0 = tm0 * TILE + r + ty;
+    tile[r + ty][tx] = res[m0 * L1 + tm1 * TILE + tx];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < TILE; r += RS) {
+    const int64_t m1 = tm1 * TILE + r + ty;
+    const int64_t k = fft2::crop(tm0 * TILE + tx + (int64_t)L0 * m1, n, nf, K);
+    if (k >= 0) out[k] = tile[tx][r + ty];
+  }
+}
+
 // ============================================================================
 // Direct sums: the three sums of every frequency evaluated term by term
 // (Sec. 1, Eq. 1), O(N_d N_f), FP64 throughout; a check of the transform at
@@ -677,8 +890,24 @@ static inline unsigned grid_for(int64_t work, int64_t cap) {
 // Dynamic LDS above the default 64 KB of a workgroup must be allowed per
 // kernel (the big FFT passes use up to kLdsBig).
 static void big_lds(const void* kern, size_t bytes) {
-  if (bytes > 65536) (void)hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)bytes);
+  // once per kernel (the largest request so far), so that a call captured
+  // into a graph after a first uncaptured one makes no attribute call
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  if (bytes <= 65536) return;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t& have = done[kern];
+  if (have >= bytes) return;
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+      hipSuccess)
+    have = bytes;
+}
+
+hipError_t launch_phihat2(double* iphi2, const double* inv_phihat, int L0, int L1, int64_t n,
+                          int64_t nf, int64_t K, hipStream_t s) {
+  hipLaunchKernelGGL(k_phihat2, dim3(grid_for(n, 1 << 30)), dim3(kThreads), 0, s, iphi2,
+                     inv_phihat, L0, L1, n, nf, K);
+  return hipGetLastError();
 }
 
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
@@ -838,6 +1067,78 @@ static void enqueue_passes(const Plan& p, const Work& w, int g0, int ng, int gri
   for (int i = 0; i < ng; ++i) in[i] = cur[i];
 }
 
+// First pass of the two-pass FFT over ng grids (b.grid[0 .. ng-1]).
+template <typename Real, int L0, int C>
+static void enqueue_fft2_first_l(const Plan& p, const Fft2Bufs<Real>& b, int ng, const Work& w,
+                                 hipStream_t st) {
+  using T2 = typename cplx<Real>::T;
+  constexpr bool H = sizeof(Real) == 8;
+  const FftPass& ps = p.pass[0];
+  auto kern = k_fft2_first<Real, L0, C, H>;
+  const size_t lds = f2_first_lds<Real>(L0, C, H);
+  big_lds(reinterpret_cast<const void*>(kern), lds);
+  hipLaunchKernelGGL(kern, dim3((unsigned)(ps.S / C), ng), dim3(C * L0 / 16), lds, st, b, ps,
+                     reinterpret_cast<const T2*>(w.tw), w.stats);
+}
+
+template <typename Real>
+static void enqueue_fft2_first(const Plan& p, const Fft2Bufs<Real>& b, int ng, const Work& w,
+                               hipStream_t st) {
+  const int L0 = p.pass[0].L, C = p.pass[0].C;
+  if (L0 == 2048 && C == 8) enqueue_fft2_first_l<Real, 2048, 8>(p, b, ng, w, st);
+  else if (L0 == 2048) enqueue_fft2_first_l<Real, 2048, 4>(p, b, ng, w, st);
+  else if (L0 == 4096 && C == 4) enqueue_fft2_first_l<Real, 4096, 4>(p, b, ng, w, st);
+  else if (L0 == 4096) enqueue_fft2_first_l<Real, 4096, 2>(p, b, ng, w, st);
+  else enqueue_fft2_first_l<Real, 8192, 2>(p, b, ng, w, st);
+}
+
+template <typename Real, int L1, int G>
+static void enqueue_fft2_last_l(const CallArgs& a, const Plan& p, const Fft2Bufs<Real>& b,
+                                const Work& w, hipStream_t st) {
+  using T2 = typename cplx<Real>::T;
+  constexpr bool H = sizeof(Real) == 8;
+  const int L0 = p.pass[0].L;
+  const int C = p.pass[0].C;
+  const FftPass& ps = p.pass[1];
+  const size_t lds = f2_last_lds<Real>(L1, G, H);
+  const T2* tw = reinterpret_cast<const T2*>(w.tw);
+  const double* lowfix = G == 3 ? w.lowfix : nullptr;
+#define MILS_F2_LAST(CC)                                                                         \
+  {                                                                                            \
+    auto kern = k_fft2_last<Real, L1, G, CC, H>;                                               \
+    big_lds(reinterpret_cast<const void*>(kern), lds);                                         \
+    hipLaunchKernelGGL(kern, dim3((unsigned)L0), dim3(G * L1 / 16), lds, st, b, ps, p, a, tw,   \
+                       w.inv_phihat2, w.stats, lowfix, w.f2out);                               \
+  }
+  if (C == 8) MILS_F2_LAST(8)
+  else if (C == 4) MILS_F2_LAST(4)
+  else MILS_F2_LAST(2)
+#undef MILS_F2_LAST
+  const int64_t nblk = (int64_t)(L0 / (G == 3 ? 64 : 32)) * (L1 / (G == 3 ? 64 : 32));
+  if (G == 3)
+    hipLaunchKernelGGL((k_fft2_out<double, 64>), dim3((unsigned)nblk), dim3(256), 0, st,
+                       reinterpret_cast<const double*>(w.f2out), a.power, L0, L1, p.n, a.nf, p.K,
+                       w.stats);
+  else
+    hipLaunchKernelGGL((k_fft2_out<double2, 32>), dim3((unsigned)nblk), dim3(256), 0, st,
+                       reinterpret_cast<const double2*>(w.f2out),
+                       reinterpret_cast<double2*>(a.sums), L0, L1, p.n, a.nf, p.K, w.stats);
+}
+
+template <typename Real>
+static void enqueue_fft2_last(const CallArgs& a, const Plan& p, const Fft2Bufs<Real>& b, int G,
+                              const Work& w, hipStream_t st) {
+  const int L1 = p.pass[1].L;
+  if (G == 3) {
+    if (L1 == 2048) enqueue_fft2_last_l<Real, 2048, 3>(a, p, b, w, st);
+    else enqueue_fft2_last_l<Real, 4096, 3>(a, p, b, w, st);
+  } else {
+    if (L1 == 2048) enqueue_fft2_last_l<Real, 2048, 1>(a, p, b, w, st);
+    else if (L1 == 4096) enqueue_fft2_last_l<Real, 4096, 1>(a, p, b, w, st);
+    else enqueue_fft2_last_l<Real, 8192, 1>(a, p, b, w, st);
+  }
+}
+
 template <typename Real>
 static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
                                 const StageHook* hook, const AuxStream* aux) {
@@ -858,6 +1159,19 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   if (a.deterministic) enqueue_det_bins(a, p, w, s);
   else enqueue_bins(a, p, w, s);
   mark(kStageBin, 0, s);
+  const int nd = (int)a.nd;
+  // two-pass plans classify the rows of both geometries before the fork:
+  // beside the other branch's persistent spread, a one-workgroup launch
+  // waits long for a free CU
+  const bool rows_first = p.fft2 && a.periodogram;
+  if (rows_first) {
+    mark(kStageSpreadF, 1, s);
+    hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
+                       w.act_rows_f, 0);
+    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
+                       w.act_rows_2f, 1);
+    mark(kStageSpreadF, 0, s);
+  }
   if (fork) {
     hipError_t e = hipEventRecord(aux->fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(s2, aux->fork, 0);
@@ -866,12 +1180,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
   const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
-  const int nd = (int)a.nd;
   // The f geometry (row classes, spread and then the first FFT pass of its
   // two grids) is the longer branch: it is launched (and captured) first.
   mark(kStageSpreadF, 1, s);
-  hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
-                     w.act_rows_f, 0);
+  if (!rows_first)
+    hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
+                       w.act_rows_f, 0);
   if (a.periodogram && a.deterministic)
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 2, true>), dim3(sgrid), dim3(kThreads), 0, s, a, p,
                        w, 0, w.act_rows_f, 0);
@@ -882,15 +1196,16 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, a, p, w, 0,
                        w.act_rows_f, 0);
   mark(kStageSpreadF, 0, s);
-  if (a.periodogram) {
+  if (a.periodogram && !p.fft2) {
     mark(kStageLow, 1, s2);
     enqueue_lowfreq(a, w, s2);
     mark(kStageLow, 0, s2);
   }
   if (a.periodogram) {
     mark(kStageSpread2F, 1, s2);
-    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd, w.rowflag_2f,
-                       w.act_rows_2f, 1);
+    if (!rows_first)
+      hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd,
+                         w.rowflag_2f, w.act_rows_2f, 1);
     if (a.deterministic)
       hipLaunchKernelGGL((k_spread_rows<Real, 2, 1, true>), dim3(sgrid), dim3(kThreads), 0, s2, a,
                          p, w, 2, w.act_rows_2f, 1);
@@ -898,6 +1213,46 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
       hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s2, a, p, w,
                          2, w.act_rows_2f, 1);
     mark(kStageSpread2F, 0, s2);
+  }
+  if (p.fft2) {
+    // two-pass register-tile FFT: the first pass of each geometry's grids on
+    // its branch, then (joined) the last pass and the transpose
+    Fft2Bufs<Real> b;
+    for (int g = 0; g < 3; ++g) {
+      b.grid[g] = reinterpret_cast<T2*>(w.grid[g < G ? g : 0]);
+      b.mid[g] = reinterpret_cast<T2*>(w.grid2[g < G ? g : 0]);
+      b.rowflag[g] = g == 2 ? w.rowflag_2f : w.rowflag_f;
+    }
+    if (fork) {
+      // both spreads first (the first pass fills every CU and would starve
+      // the other branch's small kernels), then the first pass of all three
+      // grids in one launch beside the direct sums near f = 0
+      hipError_t e = hipEventRecord(aux->mid, s2);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, aux->mid, 0);
+      if (e != hipSuccess) return e;
+      mark(kStagePass0, 1, s);
+      enqueue_fft2_first<Real>(p, b, 3, w, s);
+      mark(kStagePass0, 0, s);
+      mark(kStageLow, 1, s2);
+      enqueue_lowfreq(a, w, s2);
+      mark(kStageLow, 0, s2);
+      e = hipEventRecord(aux->join, s2);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, aux->join, 0);
+      if (e != hipSuccess) return e;
+    } else {
+      if (a.periodogram) {
+        mark(kStageLow, 1, s);
+        enqueue_lowfreq(a, w, s);
+        mark(kStageLow, 0, s);
+      }
+      mark(kStagePass0, 1, s);
+      enqueue_fft2_first<Real>(p, b, G, w, s);
+      mark(kStagePass0, 0, s);
+    }
+    mark(kStageLast, 1, s);
+    enqueue_fft2_last<Real>(a, p, b, G, w, s);
+    mark(kStageLast, 0, s);
+    return hipGetLastError();
   }
   // passes 0 .. npass-2; launch over grids [g0, g0 + ng) of the current set
   T2* cur[3];

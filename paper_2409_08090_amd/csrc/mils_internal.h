@@ -50,6 +50,7 @@ struct Plan {
   int Tb_shift;            // log2(Tb)
   int64_t nbins;           // ceil(n / Tb)
   int D;                   // rows per workgroup of the last pass
+  int fft2;                // 1: two-pass register-tile FFT (fft2.h), n = L0 * L1
   int64_t tw_count;        // complex entries in the twiddle buffer
   const void* hcoef;       // device: kernel polynomial coefficients (Real), see kHornerK
 };
@@ -144,6 +145,8 @@ struct Work {
   void* grid2[3];         // second buffers for passes >= 2
   const void* tw;         // twiddles (plan-owned)
   const double* inv_phihat;  // 1 / phihat(|m|), m = 0..K (plan-owned)
+  const double* inv_phihat2; // two-pass plans: 1 / phihat in last-pass order, n entries (plan-owned)
+  void* f2out;               // two-pass plans: last-pass results, n doubles (power) or double2 (sums)
   double* lowpart;        // per-block partial direct sums near f = 0
   double* lowfix;         // direct sums A, B, B2 near f = 0: kLowParts rows of kLowMax x 6
   uint64_t* keys;         // det_keys(nd) sort keys of the reproducible binning

@@ -123,12 +123,14 @@ struct SpreadRecords {
 // already knows that the tile lies in an active row and has written the row
 // flags), the flag of every row that starts inside the tile is written and a
 // tile of inactive rows returns at once.  acc: LDS accumulator of NG*2*tcap
-// Reals (T <= tcap); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by
+// doubles (T <= tcap; doubles for FP32 grids too: on gfx950 the LDS atomic
+// add of doubles runs at full rate while that of floats waits ~50x longer
+// per instruction); rb, re: 8 LDS ints each; sv: 2 LDS ints.  Called by
 // every thread of the workgroup (it contains barriers).
 template <typename Real, int GEO, int NG, int NT, bool KNOWN = false, bool DET = false>
 __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const Plan& p,
                             const Work& w, const DevStats& st, int gbase, unsigned char* rowflag,
-                            Real* acc, int* rb, int* re, int* sv,
+                            double* acc, int* rb, int* re, int* sv,
                             SpreadRecords<Real, NG, NT>& rec) {
   using T2 = typename cplx<Real>::T;
   const int tid = threadIdx.x;
@@ -283,8 +285,8 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
             for (int jc = 1; jc < NC; ++jc) v = v * u + hc[jc * kHornerK + off];
 #pragma unroll
             for (int g = 0; g < NG; ++g) {
-              acc[(2 * g) * tcap + x] += v * rec.h[(2 * g) * NT + i];
-              acc[(2 * g + 1) * tcap + x] += v * rec.h[(2 * g + 1) * NT + i];
+              acc[(2 * g) * tcap + x] += (double)(v * rec.h[(2 * g) * NT + i]);
+              acc[(2 * g + 1) * tcap + x] += (double)(v * rec.h[(2 * g + 1) * NT + i]);
             }
           }
         }
@@ -304,8 +306,8 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
         for (int jc = 1; jc < NC; ++jc) v = v * u + cf[jc];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          atomicAdd(&acc[(2 * g) * tcap + loc], v * rec.h[(2 * g) * NT + i]);
-          atomicAdd(&acc[(2 * g + 1) * tcap + loc], v * rec.h[(2 * g + 1) * NT + i]);
+          atomicAdd(&acc[(2 * g) * tcap + loc], (double)(v * rec.h[(2 * g) * NT + i]));
+          atomicAdd(&acc[(2 * g + 1) * tcap + loc], (double)(v * rec.h[(2 * g + 1) * NT + i]));
         }
       }
       __syncthreads();
@@ -317,8 +319,8 @@ __device__ void spread_tile(int tile, int Tt, int tcap, const CallArgs& a, const
     T2* out = reinterpret_cast<T2*>(w.grid[gbase + g]);
     for (int x = tid; x < T; x += NT) {
       T2 v;
-      v.x = acc[(2 * g) * tcap + x];
-      v.y = acc[(2 * g + 1) * tcap + x];
+      v.x = (Real)acc[(2 * g) * tcap + x];
+      v.y = (Real)acc[(2 * g + 1) * tcap + x];
       out[a0 + x] = v;
     }
   }

@@ -317,6 +317,43 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     if (err) *err = "no supported FFT factorisation for this number of frequencies";
     return false;
   }
+  // Two-pass register-tile FFT (fft2.h) in place of plans of three or more
+  // passes: n = L0 L1 with register-tile lines (L0 in 2048..8192; L1 in
+  // 2048..4096 for three grids, to 8192 for one), estimated at 0.55 (first
+  // pass: pruned reads, contiguous writes) + 1.0 (last pass) + 0.15 (the
+  // transpose of the results) of one pass over the grid.
+  int f2_l0 = 0, f2_l1 = 0;
+  if (r.fft2 && best_np >= 3 && (G == 1 || G == 3)) {
+    double f2_cost = 1e300;
+    int64_t f2_n = 0;
+    for (int64_t n : cand) {
+      if ((double)n > nlim) break;
+      // L0 = 4096 first: its first pass takes 4 columns (64-byte pieces for
+      // the last pass's reads); 8192 x 2048 measured slower at n = 2^24
+      for (int L0 : {4096, 8192, 2048}) {
+        if (n % L0) continue;
+        const int64_t L1 = n / L0;
+        if (!(L1 == 2048 || L1 == 4096 || (G == 1 && L1 == 8192))) continue;
+        const int wn = kernel_width(r.eps, (double)n / (double)r.nf, r.prec);
+        const double cost = (double)n * 1.7 + 0.049 * wn * (double)r.nf;
+        if (cost < f2_cost) {
+          f2_cost = cost;
+          f2_n = n;
+          f2_l0 = L0;
+          f2_l1 = (int)L1;
+        }
+        break;
+      }
+    }
+    if (f2_n) {
+      best_n = f2_n;
+      best_np = 2;
+      best_big = false;
+      best_len = {f2_l0, f2_l1};
+    } else {
+      f2_l0 = 0;
+    }
+  }
   p.n = best_n;
   p.sigma = (double)best_n / (double)r.nf;
   p.w = kernel_width(r.eps, p.sigma, r.prec);
@@ -329,6 +366,7 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
   p.hw = 0.5 * p.w;
   p.npass = best_np;
   int64_t before = 1;
+  p.fft2 = f2_l0 ? 1 : 0;
   for (int i = 0; i < best_np; ++i) {
     FftPass& ps = p.pass[i];
     ps.L = best_len[i];
@@ -337,6 +375,16 @@ bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {
     before *= ps.L;
     ps.nrad = radix_plan(ps.L, ps.rad);
     ps.big = best_big ? 1 : 0;
+    if (p.fft2) {
+      // first pass: C columns per workgroup of L0 / 16 threads each (the
+      // kernel's choice, at most 1024 threads); last pass: one row
+      ps.C = i == 0 ? std::min(8, 16384 / ps.L) : 1;
+
+      ps.cshift = 0;
+      while ((1 << ps.cshift) < ps.C) ++ps.cshift;
+      if (i == 1) p.D = 1;
+      continue;
+    }
     if (best_big) {
       if (i == 0) {
         ps.C = big_cols(ps.L, ps.S, r.prec, big_cmin);
@@ -412,7 +460,7 @@ void make_twiddles(Plan* p, std::vector<double>* tw) {
   for (int i = 0; i < p->npass; ++i) {
     FftPass& ps = p->pass[i];
     ps.twL_off = (int64_t)(tw->size() / 2);
-    if (ps.big) {
+    if (ps.big || p->fft2) {
       for (int x = 0; x < kTwLo; ++x) push_root(x, ps.L);
       for (int h = 0; h < (ps.L + kTwLo - 1) / kTwLo; ++h) push_root((int64_t)h * kTwLo, ps.L);
     } else {
@@ -509,8 +557,9 @@ size_t layout_work(const Plan& p, int64_t nd, int G, char* base, Work* w, bool p
   }
   const size_t cbytes = p.prec == 1 ? 8 : 16;
   for (int g = 0; g < G; ++g) x.grid[g] = take(cbytes * p.n);
-  if (p.npass >= 3)
+  if (p.npass >= 3 || p.fft2)
     for (int g = 0; g < G; ++g) x.grid2[g] = take(cbytes * p.n);
+  if (p.fft2) x.f2out = take((G == 3 ? sizeof(double) : 2 * sizeof(double)) * p.n);
   off = (off + 255) & ~(size_t)255;
   if (w) *w = x;
   return off;

@@ -21,6 +21,7 @@ struct PlanRequest {
   bool batch = false;   // plan for the batched kernels (no big passes)
   int64_t n_fixed = 0;  // use exactly this grid size (must factor), 0 = choose
   int tile_max = 0;     // largest spreading tile (cells), 0 = kTileMax
+  bool fft2 = false;    // the two-pass register-tile FFT may replace plans of 3+ passes
 };
 
 // Default upsampling factor of a precision (1.25 in both).

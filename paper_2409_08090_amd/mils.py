@@ -45,7 +45,8 @@ class mils_plan_desc(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("bin", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_uint64), ("last_rows", ctypes.c_int32),
                 ("last_lds_bytes", ctypes.c_int32), ("first_cols", ctypes.c_int32),
-                ("first_lds_bytes", ctypes.c_int32), ("big", ctypes.c_int32)]
+                ("first_lds_bytes", ctypes.c_int32), ("big", ctypes.c_int32),
+                ("fft2", ctypes.c_int32)]
 
 
 class mils_server_config(ctypes.Structure):
@@ -95,6 +96,7 @@ SIGNATURES = {
     "mils_context_create": ([ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_P)], ctypes.c_int),
     "mils_context_destroy": ([_P], ctypes.c_int),
     "mils_context_set_graphs": ([_P, ctypes.c_int], ctypes.c_int),
+    "mils_context_set_fft2": ([_P, ctypes.c_int], ctypes.c_int),
     "mils_plan_info": ([_P, ctypes.c_int64, ctypes.POINTER(mils_params),
                         ctypes.POINTER(mils_plan_desc)], ctypes.c_int),
     "mils_batch_tuning": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
@@ -194,6 +196,11 @@ class Context:
     def last_error(self) -> str:
         return load().mils_last_error(self.handle).decode()
 
+    def set_fft2(self, enable: bool):
+        """Allow (or not) the two-pass register-tile FFT for this context's
+        single-series calls."""
+        self.check(load().mils_context_set_fft2(self.handle, int(bool(enable))))
+
     def set_graphs(self, enable: bool):
         """Graph replay of repeated single-series calls (on by default)."""
         self.check(load().mils_context_set_graphs(self.handle, int(bool(enable))))
@@ -284,7 +291,7 @@ def plan_info(nd, nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01) -> dict:
            "len": list(d.len)[:d.npass], "tile": d.tile, "bin": d.bin,
            "workspace_bytes": d.workspace_bytes, "last_rows": d.last_rows,
            "last_lds_bytes": d.last_lds_bytes, "first_cols": d.first_cols,
-           "first_lds_bytes": d.first_lds_bytes, "big": d.big}
+           "first_lds_bytes": d.first_lds_bytes, "big": d.big, "fft2": d.fft2}
     ctx.close()
     return out
 

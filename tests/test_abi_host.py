@@ -135,6 +135,24 @@ def _tw2(L):
     return 64 + (L + 63) // 64
 
 
+def _check_fft2_plan(d, prec):
+    # two-pass register-tile plans: lines of 2048..8192 (three grids: last
+    # line at most 4096), workgroups of at most 1024 threads (16 elements
+    # each), LDS of the exchange lines (one half at a time in FP64: 8 bytes
+    # per element), the two-level twiddle table and (first pass) the row
+    # flags, or (last pass) the other grids' results, within 160 KB
+    elem = 16 if prec == "fp64" else 8
+    L0, L1 = d["len"]
+    assert d["npass"] == 2 and d["n"] == L0 * L1, d
+    assert L0 in (2048, 4096, 8192) and L1 in (2048, 4096), d
+    C = d["first_cols"]
+    assert C == min(8, 16384 // L0) and C * L0 // 16 <= 1024 and 3 * L1 // 16 <= 1024, d
+    lp = lambda L: L + L // 16 + 8  # noqa: E731
+    assert d["first_lds_bytes"] == C * lp(L0) * 8 + _tw2(L0) * elem + L0 <= 163840, d
+    last = max(3 * lp(L1) * 8, 3 * (L1 // 2 if prec == "fp64" else L1) * elem) + _tw2(L1) * elem
+    assert d["last_lds_bytes"] == last <= 163840, d
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fft_passes_fit_one_workgroup_over_a_size_sweep(prec):
     # LDS of a workgroup: last pass L * 3D elements + twiddles, first pass
@@ -143,6 +161,9 @@ def test_fft_passes_fit_one_workgroup_over_a_size_sweep(prec):
     elem = 16 if prec == "fp64" else 8
     for nf in sorted({int(x) for x in np.geomspace(1, 3e7, 300)}):
         d = mils.plan_info(nd=1000, nf=nf, eps=1e-9 if prec == "fp64" else 1e-5, precision=prec)
+        if d["fft2"]:
+            _check_fft2_plan(d, prec)
+            continue
         L, D, big = d["len"][-1], d["last_rows"], d["big"]
         cap, emax = (163840, 9600 if prec == "fp64" else 19200) if big else \
             (65536, 3072 if prec == "fp64" else 6144)
@@ -159,16 +180,21 @@ def test_fft_passes_fit_one_workgroup_over_a_size_sweep(prec):
 
 
 def test_large_curve_plans():
-    # the N_f = 1.2e7 curve: three small passes by default, two big ones on request
+    # the N_f = 1.2e7 curve: the two-pass register-tile FFT on a 4096 x 4096
+    # grid by default; without it three small LDS passes, or (on request)
+    # two big ones
     import subprocess, sys
     for prec, eps in (("fp64", 1e-9), ("fp32", 1e-5)):
         d = mils.plan_info(nd=1_000_000, nf=12_000_000, eps=eps, precision=prec)
-        assert d["npass"] == 3 and d["big"] == 0, d
+        assert d["npass"] == 2 and d["fft2"] == 1 and d["len"] == [4096, 4096], d
+        _check_fft2_plan(d, prec)
     code = ("from paper_2409_08090_amd import mils; "
-            "d = mils.plan_info(1_000_000, 12_000_000, 1e-9); print(d['npass'], d['big'])")
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
-                         env={**os.environ, "MILS_FFT_BIG": "1"}, check=True).stdout.split()
-    assert out == ["2", "1"]
+            "d = mils.plan_info(1_000_000, 12_000_000, 1e-9); print(d['npass'], d['big'], d['fft2'])")
+    for env, want in (({"MILS_FFT2": "0"}, ["3", "0", "0"]),
+                      ({"MILS_FFT2": "0", "MILS_FFT_BIG": "1"}, ["2", "1", "0"])):
+        out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             env={**os.environ, **env}, check=True).stdout.split()
+        assert out == want, (env, out)
 
 
 def test_kernel_error_estimate_falls_with_tolerance():
