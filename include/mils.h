@@ -203,6 +203,27 @@ int mils_trig_sums(mils_context *ctx, const double *t, const double *h, int64_t 
 int mils_periodogram(mils_context *ctx, const double *t, const double *y, const double *dy,
                      int64_t nd, const mils_params *p, double *power, void *hip_stream);
 
+/*
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the
+ * same periodogram as mils_periodogram (same arguments, results and
+ * statuses; synchronous), computed without any device allocation or free.
+ * The plan's tables and the workspace live in a fixed device scratch array
+ * of 128 MiB that each GPU the library runs on holds from its first use
+ * until the process ends (mils_plan_desc.workspace_bytes plus the plan's
+ * tables must fit: about N_f <= 1e6 in FP64, more in FP32; larger calls
+ * return MILS_ERR_UNSUPPORTED before any device work).  The context must
+ * exist already (its creation allocates its streams, events and status
+ * buffer).  Every call on a GPU shares that GPU's scratch, which keeps the
+ * last call's plan tables (a call with the same nf, eps and precision skips
+ * their upload); nothing in it needs clearing between calls.  Calls that
+ * overlap on one GPU race on the scratch: callers serialise them.  Not for
+ * a capturing stream (MILS_ERR_UNSUPPORTED).
+ */
+int mils_periodogram_noalloc(mils_context *ctx, const double *t, const double *y,
+                             const double *dy, int64_t nd, const mils_params *p, double *power,
+                             void *hip_stream);
+
 /* As mils_periodogram, but returns once the work is enqueued on hip_stream.
  * The device-side status is read by mils_context_status.
  *

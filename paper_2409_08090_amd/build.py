@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmils.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "batch.hip", "plan.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "noalloc.hip", "plan.cpp", "api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

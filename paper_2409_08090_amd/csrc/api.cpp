@@ -454,6 +454,34 @@ hipError_t launch_single_graph(mils_context* ctx, const CallArgs& a, const Plan&
   return he;
 }
 
+// Arguments of a single-series call (zero padding: the bytes serve as a
+// graph key).
+CallArgs single_args(const double* t, const double* y, const double* dy, const double* h,
+                     int64_t nd, const mils_params* p, const Plan& plan, double* power,
+                     double* sums) {
+  CallArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.t = t;
+  a.y = y;
+  a.dy = dy;
+  a.h = h;
+  a.nd = nd;
+  a.nf = p->nf;
+  a.f0 = p->f0;
+  a.df = p->df;
+  centre_frequency(p->f0, p->df, plan.K, &a.fch, &a.fcl);
+  a.kzero = zero_index(p->f0, p->df, p->nf);
+  a.norm = p->normalization;
+  a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
+  a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
+  a.dmin = p->eps;
+  a.periodogram = y ? 1 : 0;
+  a.deterministic = (p->flags & MILS_DETERMINISTIC) ? 1 : 0;
+  a.power = power;
+  a.sums = sums;
+  return a;
+}
+
 // Common body of the single-series calls.
 int run_single(mils_context* ctx, const double* t, const double* y, const double* dy,
                const double* h, int64_t nd, const mils_params* p, double* power, double* sums,
@@ -495,26 +523,7 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
   w.inv_phihat = pe->inv_phihat;
   w.inv_phihat2 = pe->inv_phihat2;
 
-  CallArgs a;
-  std::memset(&a, 0, sizeof(a));  // the bytes serve as a graph key
-  a.t = t;
-  a.y = y;
-  a.dy = dy;
-  a.h = h;
-  a.nd = nd;
-  a.nf = p->nf;
-  a.f0 = p->f0;
-  a.df = p->df;
-  centre_frequency(p->f0, p->df, plan.K, &a.fch, &a.fcl);
-  a.kzero = zero_index(p->f0, p->df, p->nf);
-  a.norm = p->normalization;
-  a.center = (p->flags & MILS_CENTER_DATA) ? 1 : 0;
-  a.fit_mean = (p->flags & MILS_FIT_MEAN) ? 1 : 0;
-  a.dmin = p->eps;
-  a.periodogram = pg ? 1 : 0;
-  a.deterministic = (p->flags & MILS_DETERMINISTIC) ? 1 : 0;
-  a.power = power;
-  a.sums = sums;
+  const CallArgs a = single_args(t, y, dy, h, nd, p, plan, power, sums);
   StageHook hook{prof_hook, ctx};
   AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join, ctx->ev_mid};
   if (!ctx->prof && ctx->aux && ctx->sg.enabled && graphs_enabled()) {
@@ -725,6 +734,132 @@ int mils_periodogram(mils_context* ctx, const double* t, const double* y, const 
   if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
   return run_single(ctx, t, y, dy, nullptr, nd, p, power, nullptr,
                     reinterpret_cast<hipStream_t>(hip_stream), true);
+}
+
+static int mils_periodogram_noalloc_impl(mils_context* ctx, const double* t, const double* y,
+                                         const double* dy, int64_t nd, const mils_params* p,
+                                         double* power, hipStream_t stream);
+
+int mils_periodogram_noalloc(mils_context* ctx, const double* t, const double* y,
+                             const double* dy, int64_t nd, const mils_params* p, double* power,
+                             void* hip_stream) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  return mils_periodogram_noalloc_impl(ctx, t, y, dy, nd, p, power,
+                                       reinterpret_cast<hipStream_t>(hip_stream));
+}
+
+// The plan whose tables occupy each GPU's no-allocation scratch (so that a
+// call repeating the previous one's sizes skips the upload).
+struct ScratchTables {
+  bool valid = false;
+  int64_t nf = 0;
+  double eps = 0.0;
+  int prec = 0;
+  bool fft2 = false;
+};
+static std::mutex g_scratch_mu;
+static ScratchTables g_scratch_tables[kNoAllocDevices];
+
+static int mils_periodogram_noalloc_impl(mils_context* ctx, const double* t, const double* y,
+                                  const double* dy, int64_t nd, const mils_params* p,
+                                  double* power, hipStream_t stream) {
+  int rc = mils_check_periodogram_args(t, y, nd, p, power);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid periodogram arguments");
+  // the plan on the host (host memory only), then the scratch layout:
+  // [1/phihat][twiddles][quadrature nodes][kernel polynomials][1/phihat in
+  // two-pass order][workspace]
+  Plan plan;
+  std::string err;
+  PlanRequest r{p->nf, p->eps, p->precision, 3};
+  r.fft2 = ctx->fft2;
+  if (!make_plan(r, &plan, &err)) return fail(ctx, MILS_ERR_UNSUPPORTED, err);
+  std::vector<double> tw;
+  make_twiddles(&plan, &tw);
+  std::vector<double> z, gphi, hc;
+  phihat_nodes(plan, &z, &gphi);
+  make_horner(plan, &hc);
+  const bool f32 = plan.prec == 1;
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t ph_b = up(sizeof(double) * (plan.K + 1));
+  const size_t tw_b = up(tw.size() * (f32 ? sizeof(float) : sizeof(double)));
+  const size_t nd_b = up(sizeof(double) * 2 * z.size());
+  const size_t hc_b = up(hc.size() * (f32 ? sizeof(float) : sizeof(double)));
+  const size_t p2_b = plan.fft2 ? up(sizeof(double) * plan.n) : 0;
+  const size_t tables = ph_b + tw_b + nd_b + hc_b + p2_b;
+  const size_t need = tables + layout_work(plan, nd, 3, nullptr, nullptr);
+  if (need > kNoAllocBytes)
+    return fail(ctx, MILS_ERR_UNSUPPORTED,
+                "the call needs " + std::to_string(need) + " bytes of device scratch; the " +
+                    "allocation-free call has " + std::to_string(kNoAllocBytes));
+  if (ctx->device < 0) return fail(ctx, MILS_ERR_DEVICE, "host-only context cannot compute");
+  if (ctx->poisoned) return fail(ctx, MILS_ERR_DEVICE, "context unusable after a device error");
+  if (capturing(stream))
+    return fail(ctx, MILS_ERR_UNSUPPORTED,
+                "the allocation-free call may upload its plan and waits for its status: it "
+                "cannot be captured");
+  hipError_t he = hipSetDevice(ctx->device);
+  if (he != hipSuccess) return hip_fail(ctx, he, "hipSetDevice");
+  char* base = static_cast<char*>(noalloc_scratch(ctx->device, &he));
+  if (!base) return hip_fail(ctx, he, "scratch address");
+  double* inv_phihat = reinterpret_cast<double*>(base);
+  char* twd = base + ph_b;
+  double* nodes = reinterpret_cast<double*>(twd + tw_b);
+  char* hdev = reinterpret_cast<char*>(nodes) + nd_b;
+  double* iphi2 = plan.fft2 ? reinterpret_cast<double*>(hdev + hc_b) : nullptr;
+  plan.hcoef = hdev;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchTables& res = g_scratch_tables[ctx->device];
+    const bool same = res.valid && res.nf == p->nf && res.eps == p->eps &&
+                      res.prec == p->precision && res.fft2 == (bool)plan.fft2;
+    if (!same) {
+      res.valid = false;
+      std::vector<float> tw32, hc32;
+      if (f32) {
+        tw32.assign(tw.begin(), tw.end());
+        hc32.assign(hc.begin(), hc.end());
+      }
+      std::vector<double> zn(z);
+      zn.insert(zn.end(), gphi.begin(), gphi.end());
+      he = hipMemcpyAsync(twd, f32 ? (const void*)tw32.data() : (const void*)tw.data(),
+                          tw.size() * (f32 ? sizeof(float) : sizeof(double)),
+                          hipMemcpyHostToDevice, stream);
+      if (he == hipSuccess)
+        he = hipMemcpyAsync(nodes, zn.data(), sizeof(double) * zn.size(), hipMemcpyHostToDevice,
+                            stream);
+      if (he == hipSuccess)
+        he = hipMemcpyAsync(hdev, f32 ? (const void*)hc32.data() : (const void*)hc.data(),
+                            hc.size() * (f32 ? sizeof(float) : sizeof(double)),
+                            hipMemcpyHostToDevice, stream);
+      if (he == hipSuccess)
+        he = launch_phihat(inv_phihat, plan.K, (double)plan.w, (double)plan.n, nodes,
+                           nodes + z.size(), (int)z.size(), stream);
+      if (he == hipSuccess && plan.fft2)
+        he = launch_phihat2(iphi2, inv_phihat, plan.pass[0].L, plan.pass[1].L, plan.n, plan.nf,
+                            plan.K, stream);
+      // the host copies of the tables go out of scope below
+      if (he == hipSuccess) he = hipStreamSynchronize(stream);
+      if (he != hipSuccess) return hip_fail(ctx, he, "scratch plan upload");
+      res.valid = true;
+      res.nf = p->nf;
+      res.eps = p->eps;
+      res.prec = p->precision;
+      res.fft2 = plan.fft2;
+    }
+  }
+  Work w{};
+  layout_work(plan, nd, 3, base + tables, &w);
+  w.tw = twd;
+  w.inv_phihat = inv_phihat;
+  w.inv_phihat2 = iphi2;
+  const CallArgs a = single_args(t, y, dy, nullptr, nd, p, plan, power, nullptr);
+  AuxStream aux{ctx->aux, ctx->ev_fork, ctx->ev_join, ctx->ev_mid};
+  he = launch_path(a, plan, w, stream, nullptr, ctx->aux ? &aux : nullptr);
+  if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+  ctx->last_stats = w.stats;
+  ctx->last_stream = stream;
+  ctx->have_pending = true;
+  return mils_context_status(ctx);
 }
 
 // Direct evaluation: statistics and the term-by-term sums; the workspace

@@ -2,6 +2,8 @@
 // and the serving loop (server.cpp).
 #pragma once
 
+#include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "../../include/mils.h"
@@ -14,3 +16,13 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
 
 // Validation shared with the public entry points (MILS_OK or the error code).
 int mils_check_params(const mils_params* p, int64_t nd);
+
+namespace mils {
+// Device scratch of mils_periodogram_noalloc (noalloc.hip): kNoAllocBytes per
+// GPU, for up to kNoAllocDevices GPUs.  noalloc_scratch returns the device
+// address of the array on `device` (looked up once per device, with that
+// device current), or NULL with *err set.
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
+constexpr int kNoAllocDevices = 64;
+void* noalloc_scratch(int device, hipError_t* err);
+}  // namespace mils

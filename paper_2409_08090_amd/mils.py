@@ -113,6 +113,8 @@ SIGNATURES = {
                          ctypes.c_int),
     "mils_periodogram_async": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params),
                                 _P, _P], ctypes.c_int),
+    "mils_periodogram_noalloc": ([_P, _P, _P, _P, ctypes.c_int64, ctypes.POINTER(mils_params),
+                                  _P, _P], ctypes.c_int),
     "mils_context_status": ([_P], ctypes.c_int),
     "mils_context_illposed": ([_P], ctypes.c_int64),
     "mils_periodogram_batch": ([_P, ctypes.c_int64, _I64P, _P, _P, _P, _I64P, _D, _D,
@@ -333,6 +335,30 @@ def periodogram(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64", normalization=
     rc = fn(ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
             ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, int(t.numel()),
             ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    ctx.check(rc)
+    return out
+
+
+def periodogram_noalloc(t, y, dy, f0, df, nf, eps=1e-9, precision="fp64",
+                        normalization="standard", center_data=True, fit_mean=True, out=None,
+                        stream=None, ctx=None):
+    """As periodogram (synchronous), through mils_periodogram_noalloc: the
+    library allocates no device memory for the call (its plan tables and
+    workspace use a fixed per-GPU scratch).  ``out`` should be given by
+    callers that must not allocate either."""
+    import torch
+    t = _dev_f64(t, "t")
+    y = _dev_f64(y, "y")
+    if dy is not None:
+        dy = _dev_f64(dy, "dy")
+    if out is None:
+        out = torch.empty(int(nf), dtype=torch.float64, device=t.device)
+    ctx = ctx or default_context(t.device.index)
+    p = make_params(f0, df, nf, eps, precision, normalization, center_data, fit_mean)
+    rc = load().mils_periodogram_noalloc(
+        ctx.handle, ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+        ctypes.c_void_p(dy.data_ptr()) if dy is not None else None, int(t.numel()),
+        ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
     ctx.check(rc)
     return out
 
