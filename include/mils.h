@@ -348,6 +348,13 @@ int mils_batch_tuning(mils_context *ctx, int64_t nf, double eps, int32_t precisi
  * batching), and read back to host memory.  Requests whose frequency count
  * exceeds the batch limit run through the single-series path on a lane.
  * Thread-safe: any host thread may submit, poll, wait and take.
+ *
+ * Plan classes: a request is computed on its frequency grid f0 + k df
+ * extended to the next class size (nf rounded up to ceil(64 * 2^(j/16)),
+ * j >= 0: at most 4.5% more frequencies), and its first nf values are
+ * returned.  Requests of any size thus share the plans of a bounded set of
+ * classes; mils_server_warm builds them before traffic arrives.  The values
+ * agree with a call at nf within the tolerance eps of the request.
  */
 typedef struct mils_server mils_server;
 
@@ -385,6 +392,8 @@ typedef struct {
   double mean_batch;  /* requests per batch */
   uint64_t failed;     /* completed requests whose status is not MILS_OK */
   uint64_t dead_lanes; /* lanes stopped by a device error (their context is unusable) */
+  uint64_t plans_built; /* plans built by the lanes (warm-up included) */
+  double plan_build_ms; /* host time the lanes spent building them */
 } mils_server_counters;
 
 /* Create a server on HIP device `device` (cfg may be NULL for defaults). */
@@ -393,6 +402,12 @@ int mils_server_create(int device, const mils_server_config *cfg, mils_server **
  * MILS_ERR_BUSY when the queue is full, MILS_ERR_OOM when the request alone
  * exceeds the budget, MILS_ERR_INVALID_ARG for bad arguments. */
 int mils_server_submit(mils_server *srv, const mils_request *req, uint64_t *ticket);
+/* Build, on every lane, the plans of every class up to nf_max for requests
+ * with the precision, tolerance, normalisation and flags of *params (its
+ * grid fields are ignored): each lane runs one short synthetic series per
+ * class.  Blocks until every lane is done; requests submitted meanwhile wait
+ * behind the warm-up.  Returns the first error a lane met. */
+int mils_server_warm(mils_server *srv, const mils_params *params, int64_t nf_max);
 /* *state = MILS_REQ_PENDING / RUNNING / DONE. */
 int mils_server_poll(mils_server *srv, uint64_t ticket, int32_t *state);
 /* Wait until the request is done (timeout_us < 0: forever); MILS_ERR_TIMEOUT otherwise. */
@@ -419,7 +434,10 @@ int mils_server_destroy(mils_server *srv);
  * path on the stream that runs it.  Stages: 0 statistics, 1 binning / sort,
  * 2 spread (geometry f), 3 spread (geometry 2f), 4-6 FFT passes through HBM
  * (first pass pruned), 7 last FFT pass fused with deconvolution, crop and
- * power, 8 direct sums near f = 0.  A periodogram runs stages 3, 8 and the
+ * power, 8 direct sums near f = 0, 9 row classes of both geometries and
+ * 10 the transpose into frequency order (9 and 10: two-pass register-tile
+ * plans, whose first pass, stage 4, transforms all three grids in one
+ * launch).  A periodogram runs stage 3, stage 8 and (multi-pass plans) the
  * first pass of the 2f grid on a second stream of the context, beside the f
  * geometry (stage 4 then counts two launches per call, and stages that
  * overlap share the GPU).  mils_profile_enable(ctx, 1) clears the
@@ -428,7 +446,7 @@ int mils_server_destroy(mils_server *srv);
  * total elapsed milliseconds and the number of timed launches to ms_total[s]
  * and launches[s] (host arrays of MILS_NUM_STAGES entries), then clears them.
  */
-enum { MILS_NUM_STAGES = 9 };
+enum { MILS_NUM_STAGES = 11 };
 int mils_profile_enable(mils_context *ctx, int enable);
 /* Stages timed while profiling is enabled: bit s for stage s (default: all).
  * Each timed stage adds two events per call; timing one stage leaves the rest

@@ -25,29 +25,51 @@ _LIB = os.path.join(_HERE, "libls_oracle.so")
 NORMALIZATIONS = {"standard": 0, "model": 1, "log": 2, "psd": 3}
 
 _lib = None
+_native = False
 
 
-def build(force: bool = True) -> str:
-    """Compile ls_oracle.c with gcc (no fast-math, no FP contraction)."""
-    if not force and os.path.exists(_LIB):
-        return _LIB
+def _target(native: bool) -> str:
+    return os.path.join(_HERE, "libls_oracle_native.so") if native else _LIB
+
+
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile ls_oracle.c with gcc (no fast-math, no FP contraction).  The
+    default build is -O2 for any x86-64 host; native=True builds -O3
+    -march=native for the machine it runs on (the timed CPU baseline).
+    Neither reassociates or contracts floating point, so both give the same
+    values."""
+    out = _target(native)
+    if not force and os.path.exists(out):
+        return out
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
     cmd = [
-        "gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11",
+        "gcc", *opt, "-fPIC", "-shared", "-fopenmp", "-std=c11",
         "-fno-fast-math", "-ffp-contract=off", "-Wall",
-        _SRC, "-o", _LIB + ".tmp", "-lm",
+        _SRC, "-o", out + ".tmp", "-lm",
     ]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def use_native() -> None:
+    """Switch this process to the -O3 -march=native build (built here on
+    first use)."""
+    global _lib, _native
+    if not _native:
+        build(force=True, native=True)
+        _native = True
+        _lib = None
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    path = _target(_native)
+    if not os.path.exists(path):
+        build(native=_native)
+    lib = ctypes.CDLL(path)
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int64)
     i32p = ctypes.POINTER(ctypes.c_int32)

@@ -9,6 +9,7 @@
 #include <cstddef>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <mutex>
 #include <string>
@@ -137,6 +138,9 @@ struct mils_context {
   int* host_status = nullptr;  // pinned
   DevStats* last_stats = nullptr;
   int64_t last_illposed = 0;  // ill-posed frequencies of the last call whose status was read
+  // plans built since the context was created, and the host time spent on them
+  int64_t plans_built = 0;
+  double plan_build_s = 0.0;
   hipStream_t last_stream = nullptr;
   bool have_pending = false;
   // per-stage event timing
@@ -235,6 +239,7 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
     *out = &it->second;
     return MILS_OK;
   }
+  const auto t_build = std::chrono::steady_clock::now();
   PlanEntry e;
   std::string err;
   PlanRequest r{nf, eps, prec, G};
@@ -303,6 +308,9 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   }
   slot = e;
   *out = &slot;
+  ++ctx->plans_built;
+  ctx->plan_build_s +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build).count();
   return MILS_OK;
 }
 
@@ -540,6 +548,11 @@ int run_single(mils_context* ctx, const double* t, const double* y, const double
 }
 
 }  // namespace
+
+void mils_context_plan_counters(const mils_context* ctx, int64_t* built, double* seconds) {
+  *built = ctx->plans_built;
+  *seconds = ctx->plan_build_s;
+}
 
 extern "C" {
 
@@ -1119,10 +1132,21 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
   const int ncls = (int)cls_n.size();
   std::vector<int64_t> cls_nf(ncls, 1);
   std::vector<int> cls_of(m);
+  std::vector<char> cls_tuned(ncls, 0);
   for (int64_t c = 0; c < m; ++c) {
     cls_of[c] = cls_of_n[{ngrid[c], tmax[c]}];
     cls_nf[cls_of[c]] = std::max<int64_t>(cls_nf[cls_of[c]], nf_off[idx[c] + 1] - nf_off[idx[c]]);
+    if (sig[c] > 1.0) cls_tuned[cls_of[c]] = 1;
   }
+  // A class of series planned with the default upsampling s takes the plan
+  // of its grid n for floor(n / s) frequencies: every member's own grid was
+  // at least s nf and at most n, so this covers all of them (kernel width for
+  // upsampling s, deconvolution table long enough), and the plan depends on
+  // the grid alone, not on which series happen to share the batch.
+  const double s_def = planner_sigma(common->eps, prec, true);
+  for (int k = 0; k < ncls; ++k)
+    if (!cls_tuned[k])
+      cls_nf[k] = std::max<int64_t>(cls_nf[k], (int64_t)std::floor((double)cls_n[k] / s_def));
   std::vector<Plan> plans(ncls);
   std::vector<const void*> twp(ncls);
   std::vector<const double*> php(ncls);
@@ -1578,9 +1602,10 @@ int mils_profile_stages(mils_context* ctx, uint32_t mask) {
 }
 
 const char* mils_profile_stage_name(int stage) {
-  static const char* names[kNumStages] = {"stats",      "bin_sort",   "spread_f",
-                                          "spread_2f",  "fft_pass_0", "fft_pass_1",
-                                          "fft_pass_2", "fft_last_power", "lowfreq"};
+  static const char* names[kNumStages] = {"stats",      "bin_sort",       "spread_f",
+                                          "spread_2f",  "fft_pass_0",     "fft_pass_1",
+                                          "fft_pass_2", "fft_last_power", "lowfreq",
+                                          "row_class",  "fft_out"};
   if (stage < 0 || stage >= kNumStages) return "";
   return names[stage];
 }

@@ -14,6 +14,10 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
                    const double* df, const mils_params* common, double* power,
                    int32_t* status_per_curve, void* hip_stream, bool use_graph);
 
+// Plans the context has built and the host seconds spent building them
+// (table generation, upload and the kernel-transform launch).
+void mils_context_plan_counters(const mils_context* ctx, int64_t* built, double* seconds);
+
 // Validation shared with the public entry points (MILS_OK or the error code).
 int mils_check_params(const mils_params* p, int64_t nd);
 

@@ -16,7 +16,9 @@ enum Stage {
   kStagePass0 = 4,  // first FFT pass (pruned), then 5, 6 for later middle passes
   kStageLast = 7,   // last FFT pass + deconvolution + power
   kStageLow = 8,    // direct sums near f = 0
-  kNumStages = 9
+  kStageRows = 9,   // row classes of both geometries (two-pass plans)
+  kStageOut = 10,   // transpose into frequency order (two-pass plans)
+  kNumStages = 11
 };
 
 // A second stream for the 2f geometry of a periodogram, with the events

@@ -1114,6 +1114,12 @@ static void enqueue_fft2_last_l(const CallArgs& a, const Plan& p, const Fft2Bufs
   else if (C == 4) MILS_F2_LAST(4)
   else MILS_F2_LAST(2)
 #undef MILS_F2_LAST
+}
+
+// The tiled transpose of the last pass's results into frequency order.
+static void enqueue_fft2_out(const CallArgs& a, const Plan& p, int G, const Work& w,
+                             hipStream_t st) {
+  const int L0 = p.pass[0].L, L1 = p.pass[1].L;
   const int64_t nblk = (int64_t)(L0 / (G == 3 ? 64 : 32)) * (L1 / (G == 3 ? 64 : 32));
   if (G == 3)
     hipLaunchKernelGGL((k_fft2_out<double, 64>), dim3((unsigned)nblk), dim3(256), 0, st,
@@ -1165,12 +1171,12 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   // waits long for a free CU
   const bool rows_first = p.fft2 && a.periodogram;
   if (rows_first) {
-    mark(kStageSpreadF, 1, s);
+    mark(kStageRows, 1, s);
     hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
                        w.act_rows_f, 0);
     hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
                        w.act_rows_2f, 1);
-    mark(kStageSpreadF, 0, s);
+    mark(kStageRows, 0, s);
   }
   if (fork) {
     hipError_t e = hipEventRecord(aux->fork, s);
@@ -1252,6 +1258,9 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
     mark(kStageLast, 1, s);
     enqueue_fft2_last<Real>(a, p, b, G, w, s);
     mark(kStageLast, 0, s);
+    mark(kStageOut, 1, s);
+    enqueue_fft2_out(a, p, G, w, s);
+    mark(kStageOut, 0, s);
     return hipGetLastError();
   }
   // passes 0 .. npass-2; launch over grids [g0, g0 + ng) of the current set

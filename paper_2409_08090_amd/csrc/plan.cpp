@@ -192,6 +192,8 @@ static double choose_sigma(double eps, int prec, bool batch) {
   return w > kMaxWidth ? 2.0 : s;
 }
 
+double planner_sigma(double eps, int prec, bool batch) { return choose_sigma(eps, prec, batch); }
+
 double kernel_beta(int w, double sigma) { return 0.97 * M_PI * w * (1.0 - 1.0 / (2.0 * sigma)); }
 
 bool make_plan(const PlanRequest& r, Plan* out, std::string* err) {

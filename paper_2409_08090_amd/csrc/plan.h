@@ -27,6 +27,10 @@ struct PlanRequest {
 // Default upsampling factor of a precision (1.25 in both).
 double default_sigma(int prec);
 
+// Smallest upsampling factor the planner uses for a tolerance when none is
+// requested (batch: a plan for the batched kernels).
+double planner_sigma(double eps, int prec, bool batch);
+
 // Kernel width for tolerance eps at upsampling sigma (clamped to [2, 20]).
 int kernel_width(double eps, double sigma, int prec);
 

@@ -9,6 +9,13 @@
 // results back.  While one lane's batch is on the device, the next
 // arrivals are packed by another lane, so batches overlap on the GPU.
 // Requests with many frequencies run through the single-series path instead.
+//
+// Plan classes: a request is computed on its frequency grid extended to the
+// next class size (nf rounded up to ceil(64 * 2^(j/16)), at most 4.5% more
+// frequencies), and the first nf values are returned.  Requests of fresh
+// sizes then share the plans (kernel width, grid, FFT factorisation and their
+// device tables) of a bounded set of classes, which mils_server_warm builds
+// ahead of traffic, instead of building a plan per size on arrival.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,10 +44,25 @@ using Clock = std::chrono::steady_clock;
 // requests packed with it.
 constexpr int64_t kBatchMaxNf = 200000;
 
+// Smallest class size >= nf: ceil(64 * 2^(j/16)) for j >= 0 (64 for nf <= 64),
+// capped at the largest frequency count a call accepts.
+int64_t nf_class(int64_t nf) {
+  constexpr int64_t kMaxNf = (int64_t)1 << 28;
+  if (nf <= 64) return 64;
+  if (nf >= kMaxNf) return nf;
+  int j = (int)std::floor(16.0 * std::log2((double)nf / 64.0));
+  if (j < 0) j = 0;
+  for (;; ++j) {
+    const int64_t v = (int64_t)std::ceil(64.0 * std::exp2((double)j / 16.0));
+    if (v >= nf) return std::min(v, kMaxNf);
+  }
+}
+
 struct Request {
   std::vector<double> t, y, dy;
   bool has_dy = false;
   mils_params p{};
+  int64_t nfc = 0;  // frequencies computed: p.nf rounded up to its plan class
   int64_t nd = 0;
   std::vector<double> power;
   int state = MILS_REQ_PENDING;
@@ -50,10 +72,10 @@ struct Request {
 };
 
 // Device bytes a request needs while in flight: inputs, output, and three
-// grids (plus their second buffers) of ~1.5 nf cells.
-uint64_t request_bytes(const mils_params& p, int64_t nd) {
+// grids (plus their second buffers) of ~1.5 nf cells (nf: the class size).
+uint64_t request_bytes(const mils_params& p, int64_t nf, int64_t nd) {
   const double c = p.precision == MILS_FP32 ? 8.0 : 16.0;
-  return (uint64_t)(24.0 * nd + 8.0 * p.nf + 2.0 * 3.0 * 1.5 * (double)p.nf * c) + 4096;
+  return (uint64_t)(24.0 * nd + 8.0 * nf + 2.0 * 3.0 * 1.5 * (double)nf * c) + 4096;
 }
 
 struct Lane {
@@ -69,6 +91,13 @@ struct Lane {
   size_t d_out_cap = 0;
   bool dead = false;
   bool injected = false;  // stopped by the fault-injection switch
+  // a plan warm-up posted by mils_server_warm (guarded by the server's mutex)
+  bool warm_req = false;
+  mils_params warm_p{};
+  int64_t warm_nf_max = 0;
+  int warm_rc = MILS_OK;
+  int64_t plans_seen = 0;  // plans built by this lane's context, last counted
+  double plan_s_seen = 0.0;
   int64_t runs = 0;       // batches run
   std::thread th;
 };
@@ -123,12 +152,16 @@ struct mils_server {
   int64_t fail_after = -1;
   std::vector<double> lat_ms;
   double first_submit = -1.0, last_done = 0.0, sums_done = 0.0;
+  uint64_t plans_built = 0;
+  double plan_build_s = 0.0;
   std::vector<std::unique_ptr<Lane>> lanes;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
   void lane_loop(Lane* L);
   void run_batch(Lane* L, std::vector<Request*>& batch);
   void run_single(Lane* L, Request* r);
+  int run_warm(Lane* L, const mils_params& p, int64_t nf_max);
+  void count_plans(Lane* L);
   void lane_died(Lane* L);
 };
 
@@ -137,16 +170,16 @@ namespace {
 bool compatible(const Request& a, const Request& b) {
   return a.p.precision == b.p.precision && a.p.eps == b.p.eps &&
          a.p.normalization == b.p.normalization && a.p.flags == b.p.flags &&
-         a.has_dy == b.has_dy && (a.p.nf > kBatchMaxNf) == (b.p.nf > kBatchMaxNf);
+         a.has_dy == b.has_dy && (a.nfc > kBatchMaxNf) == (b.nfc > kBatchMaxNf);
 }
 
 }  // namespace
 
 void mils_server::run_single(Lane* L, Request* r) {
-  const size_t nd = (size_t)r->nd, nf = (size_t)r->p.nf;
+  const size_t nd = (size_t)r->nd, nf = (size_t)r->p.nf, nfc = (size_t)r->nfc;
   int st = MILS_OK;
   if (!grow_pinned(&L->h_in, &L->h_in_cap, 3 * nd) || !grow_pinned(&L->h_out, &L->h_out_cap, nf) ||
-      !grow_device(&L->d_in, &L->d_in_cap, 3 * nd) || !grow_device(&L->d_out, &L->d_out_cap, nf)) {
+      !grow_device(&L->d_in, &L->d_in_cap, 3 * nd) || !grow_device(&L->d_out, &L->d_out_cap, nfc)) {
     st = MILS_ERR_OOM;
   } else {
     std::memcpy(L->h_in, r->t.data(), nd * sizeof(double));
@@ -157,8 +190,10 @@ void mils_server::run_single(Lane* L, Request* r) {
     if (he != hipSuccess) {
       st = MILS_ERR_DEVICE;
     } else {
+      mils_params pc = r->p;
+      pc.nf = r->nfc;
       st = mils_periodogram(L->ctx, L->d_in, L->d_in + nd, r->has_dy ? L->d_in + 2 * nd : nullptr,
-                            r->nd, &r->p, L->d_out, L->stream);
+                            r->nd, &pc, L->d_out, L->stream);
       if (st == MILS_OK || st == MILS_ERR_DEGENERATE || st == MILS_ERR_INVALID_ARG) {
         he = hipMemcpyAsync(L->h_out, L->d_out, nf * sizeof(double), hipMemcpyDeviceToHost,
                             L->stream);
@@ -178,7 +213,7 @@ void mils_server::run_batch(Lane* L, std::vector<Request*>& batch) {
   std::vector<double> f0(m), df(m);
   for (size_t i = 0; i < m; ++i) {
     nd_off[i + 1] = nd_off[i] + batch[i]->nd;
-    nf_off[i + 1] = nf_off[i] + batch[i]->p.nf;
+    nf_off[i + 1] = nf_off[i] + batch[i]->nfc;
     f0[i] = batch[i]->p.f0;
     df[i] = batch[i]->p.df;
   }
@@ -222,9 +257,67 @@ void mils_server::run_batch(Lane* L, std::vector<Request*>& batch) {
     }
     r->status = stv[i];
     if (stv[i] == MILS_OK)
-      r->power.assign(L->h_out + nf_off[i], L->h_out + nf_off[i + 1]);
+      r->power.assign(L->h_out + nf_off[i], L->h_out + nf_off[i] + r->p.nf);
   }
   if (rc == MILS_ERR_DEVICE) L->dead = true;
+}
+
+// Adds the plans this lane's context built since the last count to the
+// server's counters.  Called with mu held (only the lane's thread uses its
+// context, and it calls this between its runs).
+void mils_server::count_plans(Lane* L) {
+  int64_t built = 0;
+  double sec = 0.0;
+  mils_context_plan_counters(L->ctx, &built, &sec);
+  plans_built += (uint64_t)(built - L->plans_seen);
+  plan_build_s += sec - L->plan_s_seen;
+  L->plans_seen = built;
+  L->plan_s_seen = sec;
+}
+
+// Runs every plan class up to nf_max once on this lane (parameters p apart
+// from the grid): a one-series batch for the batched classes and a
+// single-series call for the larger ones, on a short synthetic series (the
+// single-series classes with nf / 12 points, so that the workspace also
+// grows ahead of traffic).  Returns the first error.
+int mils_server::run_warm(Lane* L, const mils_params& p, int64_t nf_max) {
+  const int64_t top = nf_class(nf_max);
+  std::vector<double> h;
+  for (int64_t v = nf_class(1);; v = nf_class(v + 1)) {
+    const bool single = v > kBatchMaxNf;
+    const int64_t nd = single ? std::max<int64_t>(64, v / 12) : 64;
+    // sorted times on [0, 20) with irregular spacing, a sinusoid, unit errors
+    h.resize(3 * (size_t)nd);
+    for (int64_t j = 0; j < nd; ++j) {
+      const double u = ((double)j + 0.5 + 0.4 * std::sin(7.1 * (double)j)) / (double)nd;
+      h[j] = 20.0 * u;
+      h[nd + j] = std::sin(2.3 * h[j]) + 0.1 * std::cos(17.0 * (double)j);
+      h[2 * nd + j] = 1.0;
+    }
+    if (!grow_device(&L->d_in, &L->d_in_cap, 3 * (size_t)nd) ||
+        !grow_device(&L->d_out, &L->d_out_cap, (size_t)v))
+      return MILS_ERR_OOM;
+    if (hipMemcpyAsync(L->d_in, h.data(), 3 * (size_t)nd * sizeof(double), hipMemcpyHostToDevice,
+                       L->stream) != hipSuccess)
+      return MILS_ERR_DEVICE;
+    mils_params q = p;
+    q.nf = v;
+    q.f0 = q.df = 0.01;
+    int rc;
+    if (single) {
+      rc = mils_periodogram(L->ctx, L->d_in, L->d_in + nd, L->d_in + 2 * nd, nd, &q, L->d_out,
+                            L->stream);
+    } else {
+      const int64_t nd_off[2] = {0, nd}, nf_off[2] = {0, v};
+      int32_t st = MILS_OK;
+      rc = mils_batch_run(L->ctx, 1, nd_off, L->d_in, L->d_in + nd, L->d_in + 2 * nd, nf_off,
+                          &q.f0, &q.df, &q, L->d_out, &st, L->stream, false);
+    }
+    if (rc != MILS_OK && rc != MILS_ERR_DEGENERATE) return rc;
+    if (hipStreamSynchronize(L->stream) != hipSuccess) return MILS_ERR_DEVICE;
+    if (v >= top) break;
+  }
+  return MILS_OK;
 }
 
 // A lane whose context took a device error stops; once no lane is left, the
@@ -257,8 +350,24 @@ void mils_server::lane_loop(Lane* L) {
   const auto tick = std::chrono::microseconds(cfg.tick_us);
   std::unique_lock<std::mutex> lk(mu);
   while (!stop && !L->dead) {
-    cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    cv_work.wait(lk, [&] { return stop || !pending.empty() || L->warm_req; });
     if (stop) break;
+    if (L->warm_req) {
+      const mils_params wp = L->warm_p;
+      const int64_t wmax = L->warm_nf_max;
+      lk.unlock();
+      const int rc = run_warm(L, wp, wmax);
+      lk.lock();
+      L->warm_rc = rc;
+      L->warm_req = false;
+      if (rc == MILS_ERR_DEVICE) {
+        L->dead = true;
+        lane_died(L);
+      }
+      count_plans(L);
+      cv_done.notify_all();
+      continue;
+    }
     // let a small batch grow for up to one tick
     if ((int)pending.size() < cfg.max_batch) {
       const Request& head = *reqs[pending.front()];
@@ -271,15 +380,15 @@ void mils_server::lane_loop(Lane* L) {
     }
     // admit compatible requests in arrival order while the budget allows
     Request* first = reqs[pending.front()].get();
-    const bool single = first->p.nf > kBatchMaxNf;
+    const bool single = first->nfc > kBatchMaxNf;
     std::vector<uint64_t> take;
     std::vector<Request*> batch;
     uint64_t need = 0, data_bytes = 0, slot_max = 0;
     for (uint64_t tk : pending) {
       Request* r = reqs[tk].get();
       if (!compatible(*first, *r)) continue;
-      const uint64_t rb = request_bytes(r->p, r->nd);
-      const uint64_t d2 = data_bytes + (uint64_t)(24 * r->nd + 8 * r->p.nf);
+      const uint64_t rb = request_bytes(r->p, r->nfc, r->nd);
+      const uint64_t d2 = data_bytes + (uint64_t)(24 * r->nd + 8 * r->nfc);
       const uint64_t s2 = std::max(slot_max, rb);
       const uint64_t n2 = d2 + std::min<uint64_t>(batch.size() + 1, 2 * (uint64_t)num_cu) * s2;
       if (inflight + n2 > cfg.hbm_budget_bytes) break;
@@ -333,6 +442,7 @@ void mils_server::lane_loop(Lane* L) {
       if (r->status == MILS_OK) sums_done += (double)r->nd * (double)r->p.nf;
       else ++failed;
     }
+    count_plans(L);
     if (L->dead) lane_died(L);
     last_done = t_done;
     cv_done.notify_all();
@@ -394,7 +504,8 @@ int mils_server_submit(mils_server* srv, const mils_request* req, uint64_t* tick
   int rc = mils_check_params(&req->params, req->nd);
   if (rc != MILS_OK) return rc;
   if (req->params.flags & MILS_DETERMINISTIC) return MILS_ERR_UNSUPPORTED;
-  const uint64_t rb = request_bytes(req->params, req->nd);
+  const int64_t nfc = nf_class(req->params.nf);
+  const uint64_t rb = request_bytes(req->params, nfc, req->nd);
   auto r = std::make_unique<Request>();
   const size_t nd = (size_t)req->nd;
   r->t.assign(req->t, req->t + nd);
@@ -402,11 +513,12 @@ int mils_server_submit(mils_server* srv, const mils_request* req, uint64_t* tick
   r->has_dy = req->dy != nullptr;
   if (r->has_dy) r->dy.assign(req->dy, req->dy + nd);
   r->p = req->params;
+  r->nfc = nfc;
   r->nd = req->nd;
   std::lock_guard<std::mutex> lk(srv->mu);
   if (srv->stop) return MILS_ERR_CANCELLED;
   if (srv->dead_lanes == srv->lanes.size()) return MILS_ERR_DEVICE;
-  if (rb + (uint64_t)(24 * req->nd + 8 * req->params.nf) > srv->cfg.hbm_budget_bytes) {
+  if (rb + (uint64_t)(24 * req->nd + 8 * nfc) > srv->cfg.hbm_budget_bytes) {
     ++srv->rejected;
     return MILS_ERR_OOM;
   }
@@ -423,6 +535,39 @@ int mils_server_submit(mils_server* srv, const mils_request* req, uint64_t* tick
   *ticket = tk;
   srv->cv_work.notify_one();
   return MILS_OK;
+}
+
+int mils_server_warm(mils_server* srv, const mils_params* params, int64_t nf_max) {
+  if (!srv || !params || nf_max < 1) return MILS_ERR_INVALID_ARG;
+  mils_params p = *params;
+  p.nf = nf_class(nf_max);
+  int rc = mils_check_params(&p, 64);
+  if (rc != MILS_OK) return rc;
+  if (p.flags & MILS_DETERMINISTIC) return MILS_ERR_UNSUPPORTED;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  if (srv->stop) return MILS_ERR_CANCELLED;
+  for (auto& L : srv->lanes) {
+    if (L->dead) continue;
+    L->warm_p = p;
+    L->warm_nf_max = nf_max;
+    L->warm_rc = MILS_OK;
+    L->warm_req = true;
+  }
+  srv->cv_work.notify_all();
+  srv->cv_done.wait(lk, [&] {
+    for (auto& L : srv->lanes)
+      if (L->warm_req && !L->dead && !srv->stop) return false;
+    return true;
+  });
+  rc = MILS_OK;
+  int alive = 0;
+  for (auto& L : srv->lanes) {
+    if (L->dead) continue;
+    ++alive;
+    if (rc == MILS_OK && L->warm_rc != MILS_OK) rc = L->warm_rc;
+  }
+  if (rc == MILS_OK && !alive) rc = MILS_ERR_DEVICE;
+  return rc;
 }
 
 int mils_server_poll(mils_server* srv, uint64_t ticket, int32_t* state) {
@@ -491,6 +636,8 @@ int mils_server_stats(mils_server* srv, mils_server_counters* out) {
     out->mean_batch = srv->batches ? (double)srv->batched_reqs / (double)srv->batches : 0.0;
     out->failed = srv->failed;
     out->dead_lanes = srv->dead_lanes;
+    out->plans_built = srv->plans_built;
+    out->plan_build_ms = srv->plan_build_s * 1e3;
     const double span = srv->last_done - srv->first_submit;
     out->sums_per_s = span > 0 ? srv->sums_done / span : 0.0;
     lat = srv->lat_ms;

@@ -73,7 +73,8 @@ class mils_server_counters(ctypes.Structure):
                 ("latency_p50_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
                 ("latency_max_ms", ctypes.c_double), ("sums_per_s", ctypes.c_double),
                 ("mean_batch", ctypes.c_double), ("failed", ctypes.c_uint64),
-                ("dead_lanes", ctypes.c_uint64)]
+                ("dead_lanes", ctypes.c_uint64), ("plans_built", ctypes.c_uint64),
+                ("plan_build_ms", ctypes.c_double)]
 
 
 class MilsError(RuntimeError):
@@ -140,11 +141,12 @@ SIGNATURES = {
     "mils_server_take": ([_P, ctypes.c_uint64, _P, ctypes.POINTER(mils_request_stats)],
                          ctypes.c_int),
     "mils_server_stats": ([_P, ctypes.POINTER(mils_server_counters)], ctypes.c_int),
+    "mils_server_warm": ([_P, ctypes.POINTER(mils_params), ctypes.c_int64], ctypes.c_int),
     "mils_server_last_error": ([_P], ctypes.c_char_p),
     "mils_server_destroy": ([_P], ctypes.c_int),
 }
 
-MILS_NUM_STAGES = 9
+MILS_NUM_STAGES = 11
 
 
 def load():
@@ -594,6 +596,13 @@ class Server:
         tk = ctypes.c_uint64()
         rc = load().mils_server_submit(self.handle, ctypes.byref(req), ctypes.byref(tk))
         return rc, tk.value
+
+    def warm(self, nf_max, eps=1e-9, precision="fp64", normalization="standard",
+             center_data=True, fit_mean=True):
+        """Build every lane's plans of the classes up to nf_max (blocking)."""
+        p = make_params(0.01, 0.01, int(nf_max), eps, precision, normalization, center_data,
+                        fit_mean)
+        return load().mils_server_warm(self.handle, ctypes.byref(p), int(nf_max))
 
     def poll(self, ticket):
         st = ctypes.c_int32()

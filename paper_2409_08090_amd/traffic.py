@@ -27,8 +27,9 @@ from collections import defaultdict
 COPY_BYTES = 1 << 30
 STAGE_OF = [
     ("k_stats", "stats"), ("k_lowfreq", "lowfreq"), ("k_bins_sorted", "bin_sort"),
-    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_row_class<2>", "spread_2f"),
-    ("k_row_class<1>", "spread_f"), ("k_fft_last", "fft_last_power"),
+    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_row_class", "row_class"),
+    ("k_fft_last", "fft_last_power"), ("k_fft2_first", "fft_pass_0"),
+    ("k_fft2_last", "fft_last_power"), ("k_fft2_out", "fft_out"),
 ]
 
 
@@ -63,10 +64,12 @@ def _is_2f(name):
 
 def stage_bytes(disp, scale):
     """Average scaled bytes per periodogram of each stage, over the complete
-    periodograms in the trace (each starts with k_stats).  A periodogram
+    periodograms in the trace (each starts with k_stats).  A multi-pass plan
     launches the first FFT pass twice (the 2f grid, then the two f grids,
     after the 2f spread): those two make stage fft_pass_0, and the i-th
-    later pass launch is fft_pass_i."""
+    later pass launch is fft_pass_i.  A two-pass register-tile plan has one
+    first-pass launch (fft_pass_0), its last pass and the transpose
+    (fft_out).  The row classes of both geometries make stage row_class."""
     steps = []
     cur = None
     npass = 0
@@ -111,8 +114,8 @@ def copy_scale(disp):
 # The sources the single-series kernels are compiled from, and the planner
 # that fixes their launch shapes: a change to any of them makes stored
 # counter readings stale.
-SINGLE_PATH_SOURCES = ("device_math.h", "fft_core.h", "kernels.h", "kernels.hip",
-                       "mils_internal.h", "path_device.h", "plan.cpp", "plan.h")
+SINGLE_PATH_SOURCES = ("device_math.h", "fft2.h", "fft2_index.h", "fft_core.h", "kernels.h",
+                       "kernels.hip", "mils_internal.h", "path_device.h", "plan.cpp", "plan.h")
 
 
 def kernel_source_hash(root):

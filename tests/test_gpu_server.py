@@ -192,3 +192,30 @@ def test_shutdown_with_requests_in_flight():
     t0 = time.time()
     srv.close()  # cancels what has not run, waits for what is on the device
     assert time.time() - t0 < 60
+
+
+def test_plan_classes_after_warm():
+    """After mils_server_warm, requests of fresh sizes (batched and single)
+    build no plan; results of sizes between classes match the oracle."""
+    srv = mils.Server(0, lanes=2)
+    for prec in ("fp32", "fp64"):
+        assert srv.warm(400_000, eps=EPS[prec], precision=prec) == mils.MILS_OK
+    s0 = srv.stats()
+    assert s0["plans_built"] > 0 and s0["plan_build_ms"] > 0
+    rng = np.random.default_rng(11)
+    cs = []
+    for nd in (57, 333, 1201, 9999, 20_011, 31_337):  # nf = 12 nd: off the class sizes
+        for prec in ("fp32", "fp64"):
+            c = workloads.batch_curve(rng, nd)
+            cs.append((c, prec, submit(srv, c, prec)))
+    for c, prec, tk in cs:
+        rc, p, _ = result(srv, tk, c.nf)
+        assert rc == mils.MILS_OK and p.shape == (c.nf,)
+        k = np.unique(np.concatenate([np.arange(50), np.arange(c.nf - 50, c.nf),
+                                      rng.integers(0, c.nf, 200), np.argsort(p)[-5:]]))
+        ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+        assert rel(p[k], ref) <= TOL[prec], (c.nd, prec)
+    s1 = srv.stats()
+    assert s1["plans_built"] == s0["plans_built"], (s0, s1)
+    assert s1["failed"] == 0
+    srv.close()

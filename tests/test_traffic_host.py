@@ -26,8 +26,8 @@ def test_stage_bytes_per_periodogram():
     disp = [(0, "void mils::k_phihat(...)", 100.0)] + _step() + _step(3.0)
     got = traffic.stage_bytes(disp, 1.0 / 1024.0)
     # the average of the two periodograms (scales 1 and 3)
-    want = {"stats": 2, "bin_sort": 2, "lowfreq": 4, "spread_2f": 6, "spread_f": 8,
-            "fft_pass_0": 24, "fft_pass_1": 17, "fft_last_power": 19}
+    want = {"stats": 2, "bin_sort": 2, "lowfreq": 4, "spread_2f": 5, "spread_f": 7,
+            "row_class": 2, "fft_pass_0": 24, "fft_pass_1": 17, "fft_last_power": 19}
     assert set(got) == set(want)
     for k, v in want.items():
         assert abs(got[k] - 2.0 * v) < 1e-9, k
@@ -44,10 +44,29 @@ def test_spread_names_with_more_template_arguments():
     step = [(0, n.replace("<double, 2, 1>", "<double, 2, 1, false>")
              .replace("<double, 1, 2>", "<double, 1, 2, false>"), k) for _, n, k in _step()]
     got = traffic.stage_bytes(step, 1.0 / 1024.0)
-    assert abs(got["spread_2f"] - 6.0) < 1e-9 and abs(got["fft_pass_0"] - 24.0) < 1e-9
+    assert abs(got["spread_2f"] - 5.0) < 1e-9 and abs(got["fft_pass_0"] - 24.0) < 1e-9
 
 
 def test_copy_scale():
     disp = [(0, "__amd_rocclr_copyBuffer", traffic.COPY_BYTES / 1024.0 / 2.0)]
     assert abs(traffic.copy_scale(disp) - 2.0) < 1e-12
     assert traffic.copy_scale([(0, "k_stats", 1.0)]) is None
+
+
+def test_two_pass_plan_stages():
+    step = [
+        ("void mils::k_stats(mils::CallArgs, mils::Work)", 1),
+        ("void mils::k_bins_sorted(mils::CallArgs, mils::Plan, mils::Work)", 2),
+        ("void mils::k_row_class<1>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_row_class<2>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_spread_rows<double, 1, 2, false>(mils::CallArgs, mils::Plan, mils::Work)", 7),
+        ("void mils::k_spread_rows<double, 2, 1, false>(mils::CallArgs, mils::Plan, mils::Work)", 5),
+        ("void mils::k_fft2_first<double, 4096, 4, true>(...)", 30),
+        ("void mils::k_lowfreq(mils::CallArgs, mils::Work)", 3),
+        ("void mils::k_fft2_last<double, 4096, 3, 4, true>(...)", 40),
+        ("void mils::k_fft2_out<double, 64>(...)", 6),
+    ]
+    got = traffic.stage_bytes([(0, n, k) for n, k in step], 1.0 / 1024.0)
+    want = {"stats": 1, "bin_sort": 2, "row_class": 2, "spread_f": 7, "spread_2f": 5,
+            "fft_pass_0": 30, "lowfreq": 3, "fft_last_power": 40, "fft_out": 6}
+    assert got == {k: float(v) for k, v in want.items()}
