@@ -692,7 +692,8 @@ int mils_plan_info(mils_context* ctx, int64_t nd, const mils_params* p, mils_pla
       const bool h = pl.prec == 0;
       out->first_lds_bytes = (int32_t)(pl.prec == 1 ? f2_first_lds<float>(pl.pass[0].L, pl.pass[0].C, h)
                                                     : f2_first_lds<double>(pl.pass[0].L, pl.pass[0].C, h));
-      out->last_lds_bytes = (int32_t)(pl.prec == 1 ? f2_last_lds<float>(pl.pass[1].L, 3, h)
+      // FP32: the three grids of a row one after another (one exchange line)
+      out->last_lds_bytes = (int32_t)(pl.prec == 1 ? f2_last_seq_lds<float>(pl.pass[1].L, false)
                                                    : f2_last_lds<double>(pl.pass[1].L, 3, h));
     }
   }

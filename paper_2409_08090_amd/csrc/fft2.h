@@ -150,4 +150,12 @@ __host__ __device__ constexpr size_t f2_last_lds(int L1, int G, bool halves) {
   return (ex > comb ? ex : comb) + (size_t)tw2_count(L1) * 2 * sizeof(Real);
 }
 
+// LDS bytes of a last-pass workgroup that transforms the three grids of a
+// row one after another: one exchange line and the twiddle table of L1.
+template <typename Real>
+__host__ __device__ constexpr size_t f2_last_seq_lds(int L1, bool halves) {
+  return (size_t)fft2::line_pitch(L1) * (halves ? sizeof(Real) : 2 * sizeof(Real)) +
+         (size_t)tw2_count(L1) * 2 * sizeof(Real);
+}
+
 }  // namespace mils

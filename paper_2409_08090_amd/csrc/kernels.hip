@@ -345,30 +345,45 @@ __global__ __launch_bounds__(kThreads) void k_det_gather(CallArgs a, Plan p, Wor
 // Rows that no kernel support reaches are not written (nor visited); their
 // flag tells the first FFT pass to treat them as zero.
 // ============================================================================
-// Row classification for the spread: the flag of every row of geometry GEO
+// Row classification for the spread: the flag of every row of a geometry
 // (1 if a kernel support reaches it) and the list of active rows in order.
-// One workgroup of kRowThreads threads; thread i takes the rows
-// [i*rpt, (i+1)*rpt) (rpt = ceil(nrows / kRowThreads)), so their order
+// The compaction is one workgroup of kRowThreads threads; thread i takes the
+// rows [i*rpt, (i+1)*rpt) (rpt = ceil(nrows / kRowThreads)), so their order
 // survives one scan of the per-thread counts.
 constexpr int kRowThreads = 1024;
 static_assert(kRowsMax <= kRowThreads * 32, "row flags of a thread fit one word");
-template <int GEO>
-__global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int nd,
-                                                           unsigned char* rowflag, int* act_rows,
-                                                           int slot) {
+// Row classes, in two launches for geometries geo0 .. geo0 + gridDim.y - 1
+// (0: f, 1: 2f).  k_row_flags: one thread per row of the [nrows][S1] view
+// sets its flag (whether any kernel support of the geometry reaches it);
+// k_row_compact: one workgroup per geometry lists the active rows in order
+// and stores their count in nact[geometry].
+__global__ __launch_bounds__(256) void k_row_flags(Plan p, Work w, int nd, int geo0) {
+  const DevStats* st = w.stats;
+  if (st->status != 0) return;
+  const int geo = geo0 + (int)blockIdx.y;
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= p.nrows) return;
+  const int h = (int)ceil(p.hw) + 1;
+  const bool active = geo == 0 ? row_active<1>(r, h, p, w.bin_start, nd)
+                               : row_active<2>(r, h, p, w.bin_start, nd);
+  (geo == 0 ? w.rowflag_f : w.rowflag_2f)[r] = (unsigned char)active;
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_row_compact(Plan p, Work w, int geo0) {
   __shared__ int scan[kRowThreads];
   const DevStats* st = w.stats;
   if (st->status != 0) return;
+  const int geo = geo0 + (int)blockIdx.x;
+  const unsigned char* rowflag = geo == 0 ? w.rowflag_f : w.rowflag_2f;
+  int* act_rows = geo == 0 ? w.act_rows_f : w.act_rows_2f;
   const int tid = threadIdx.x;
   const int nrows = (int)p.nrows;
   const int rpt = (nrows + kRowThreads - 1) / kRowThreads;
   const int r0 = tid * rpt;
-  const int h = (int)ceil(p.hw) + 1;
   unsigned flags = 0;  // bit i: row r0 + i is active (rpt <= 32)
   int cnt = 0;
   for (int i = 0; i < rpt && r0 + i < nrows; ++i) {
-    const int active = row_active<GEO>(r0 + i, h, p, w.bin_start, nd);
-    rowflag[r0 + i] = (unsigned char)active;
+    const int active = rowflag[r0 + i] != 0;
     flags |= (unsigned)active << i;
     cnt += active;
   }
@@ -383,11 +398,18 @@ __global__ __launch_bounds__(kRowThreads) void k_row_class(Plan p, Work w, int n
   int pos = scan[tid] - cnt;
   for (int i = 0; i < rpt && r0 + i < nrows; ++i)
     if ((flags >> i) & 1u) act_rows[pos++] = r0 + i;
-  if (tid == kRowThreads - 1) w.nact[slot] = scan[tid];
+  if (tid == kRowThreads - 1) w.nact[geo] = scan[tid];
+}
+
+static void enqueue_row_class(const Plan& p, const Work& w, int nd, int geo0, int ngeo,
+                              hipStream_t s) {
+  const unsigned nb = (unsigned)((p.nrows + 255) / 256);
+  hipLaunchKernelGGL(k_row_flags, dim3(nb, (unsigned)ngeo), dim3(256), 0, s, p, w, nd, geo0);
+  hipLaunchKernelGGL(k_row_compact, dim3((unsigned)ngeo), dim3(kRowThreads), 0, s, p, w, geo0);
 }
 
 // Spreading over the tiles of the active rows only (their list and count come
-// from k_row_class): a fixed grid of workgroups takes tiles blk, blk + grid,
+// from k_row_compact): a fixed grid of workgroups takes tiles blk, blk + grid,
 // ...; every tile is written by exactly one workgroup, so the result does not
 // depend on scheduling.  T divides the row length S1 here.
 template <typename Real, int GEO, int NG, bool DET = false>
@@ -728,6 +750,78 @@ __global__ __launch_bounds__(G * L1 / 16, G == 3 ? 3 : 2) void k_fft2_last(Fft2B
       sums[m1] = make_double2((double)A.x * ipv[j], (double)A.y * ipv[j]);
     }
   }
+}
+
+// Last pass of a periodogram, one row m0 per workgroup of L1 / 16 threads
+// that transform the row of the three grids one after another (the next
+// grid's loads in flight meanwhile) and keep every result in registers:
+// thread t then holds A, B and B2 of the same 16 modes m = m0 + L0 m1,
+// m1 = t + (L1/16) j, and computes their power with no exchange.  The
+// workgroup needs one exchange line of LDS, so that several fit a CU and one
+// workgroup's loads overlap another's transform.  Power of mode m goes to
+// out[m0 L1 + m1]; cropped modes are not written.
+template <typename Real, int L1, int C, bool HALVES>
+__global__ __launch_bounds__(L1 / 16, sizeof(Real) == 8 ? 1 : 2) void k_fft2_last_seq(Fft2Bufs<Real> b, FftPass ps,
+                                                             Plan pl, CallArgs a,
+                                                             const typename cplx<Real>::T* tw,
+                                                             const double* iphi2,
+                                                             const DevStats* stp,
+                                                             const double* lowfix, double* pwout) {
+  using T2 = typename cplx<Real>::T;
+  using Lds = typename std::conditional<HALVES, Real, T2>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (stp->status != 0) return;
+  constexpr int TL = L1 / 16, LP = fft2::line_pitch(L1);
+  const int t = threadIdx.x;
+  const int64_t L0 = ps.P;
+  const int64_t m0 = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
+  Lds* ex = reinterpret_cast<Lds*>(smem);
+  T2* twl = reinterpret_cast<T2*>(smem + (size_t)LP * sizeof(Lds));
+  T2 va[16], vb[16], vc[16];
+  auto load = [&](T2(&v)[16], int g) {
+    const T2* in = b.mid[g] + m0 * C;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int sc = t + q * TL;
+      v[q] = in[(int64_t)(sc / C) * (L0 * C) + (sc & (C - 1))];
+    }
+  };
+  load(va, 0);
+  load(vb, 1);
+  for (int x = t; x < tw2_count(L1); x += TL) twl[x] = tw[ps.twL_off + x];
+  __syncthreads();
+  f2_line<L1, HALVES>(va, t, ex, twl);
+  load(vc, 2);
+  f2_line<L1, HALVES>(vb, t, ex, twl);
+  f2_line<L1, HALVES>(vc, t, ex, twl);
+  const int64_t n = pl.n, nf = a.nf, K = pl.K;
+  const DevStats st = *stp;
+  const double* ip = iphi2 + m0 * L1;
+  double* pw = pwout + m0 * L1;
+  int nan_count = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int64_t m1 = t + TL * j;
+    const int64_t kout = fft2::crop(m0 + L0 * m1, n, nf, K);
+    if (kout < 0) continue;
+    const double iv = ip[m1];
+    const int r = f2_reg_of<L1>(j);
+    double s6[6] = {(double)va[r].x * iv, (double)va[r].y * iv, (double)vb[r].x * iv,
+                    (double)vb[r].y * iv, (double)vc[r].x * iv, (double)vc[r].y * iv};
+    const int64_t q = kout - st.k_lo;
+    const bool low = q >= 0 && q < st.nlow;
+    if (low) {
+      for (int c6 = 0; c6 < 6; ++c6) s6[c6] = lowfix[6 * q + c6];
+      for (int pp = 1; pp < kLowParts; ++pp)
+        for (int c6 = 0; c6 < 6; ++c6) s6[c6] += lowfix[pp * 6 * kLowMax + 6 * q + c6];
+    }
+    double p = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean,
+                        low ? 0.0 : a.dmin);
+    if (kout == a.kzero) p = 0.0;
+    else if (p != p) ++nan_count;
+    pw[m1] = p;
+  }
+  if (nan_count) atomicAdd(const_cast<int*>(&stp->nill), nan_count);
 }
 
 // Results of the last pass, [L0][L1] by (m0, m1), into frequency order:
@@ -1104,7 +1198,13 @@ static void enqueue_fft2_last_l(const CallArgs& a, const Plan& p, const Fft2Bufs
   const T2* tw = reinterpret_cast<const T2*>(w.tw);
   const double* lowfix = G == 3 ? w.lowfix : nullptr;
 #define MILS_F2_LAST(CC)                                                                         \
-  {                                                                                            \
+  if (G == 3 && !H) {                                                                          \
+    auto kern = k_fft2_last_seq<Real, L1, CC, H>;                                              \
+    const size_t lds3 = f2_last_seq_lds<Real>(L1, H);                                          \
+    big_lds(reinterpret_cast<const void*>(kern), lds3);                                        \
+    hipLaunchKernelGGL(kern, dim3((unsigned)L0), dim3(L1 / 16), lds3, st, b, ps, p, a, tw,      \
+                       w.inv_phihat2, w.stats, lowfix, reinterpret_cast<double*>(w.f2out));    \
+  } else {                                                                                     \
     auto kern = k_fft2_last<Real, L1, G, CC, H>;                                               \
     big_lds(reinterpret_cast<const void*>(kern), lds);                                         \
     hipLaunchKernelGGL(kern, dim3((unsigned)L0), dim3(G * L1 / 16), lds, st, b, ps, p, a, tw,   \
@@ -1172,10 +1272,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   const bool rows_first = p.fft2 && a.periodogram;
   if (rows_first) {
     mark(kStageRows, 1, s);
-    hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
-                       w.act_rows_f, 0);
-    hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
-                       w.act_rows_2f, 1);
+    enqueue_row_class(p, w, nd, 0, 2, s);
     mark(kStageRows, 0, s);
   }
   if (fork) {
@@ -1190,8 +1287,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   // two grids) is the longer branch: it is launched (and captured) first.
   mark(kStageSpreadF, 1, s);
   if (!rows_first)
-    hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
-                       w.act_rows_f, 0);
+    enqueue_row_class(p, w, nd, 0, 1, s);
   if (a.periodogram && a.deterministic)
     hipLaunchKernelGGL((k_spread_rows<Real, 1, 2, true>), dim3(sgrid), dim3(kThreads), 0, s, a, p,
                        w, 0, w.act_rows_f, 0);
@@ -1210,8 +1306,7 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   if (a.periodogram) {
     mark(kStageSpread2F, 1, s2);
     if (!rows_first)
-      hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s2, p, w, nd,
-                         w.rowflag_2f, w.act_rows_2f, 1);
+      enqueue_row_class(p, w, nd, 1, 1, s2);
     if (a.deterministic)
       hipLaunchKernelGGL((k_spread_rows<Real, 2, 1, true>), dim3(sgrid), dim3(kThreads), 0, s2, a,
                          p, w, 2, w.act_rows_2f, 1);
@@ -1344,10 +1439,7 @@ static hipError_t launch_weight_sums_t(const CallArgs& aw, const Plan& p, const 
   const int64_t ntiles = (p.S1 / p.T) * p.nrows;
   const unsigned sgrid = (unsigned)(ntiles < kSpreadGrid ? ntiles : kSpreadGrid);
   const int nd = (int)aw.nd;
-  hipLaunchKernelGGL(k_row_class<1>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_f,
-                     w.act_rows_f, 0);
-  hipLaunchKernelGGL(k_row_class<2>, dim3(1), dim3(kRowThreads), 0, s, p, w, nd, w.rowflag_2f,
-                     w.act_rows_2f, 1);
+  enqueue_row_class(p, w, nd, 0, 2, s);
   hipLaunchKernelGGL((k_spread_rows<Real, 1, 1>), dim3(sgrid), dim3(kThreads), 0, s, aw, p, w, 1,
                      w.act_rows_f, 0);
   hipLaunchKernelGGL((k_spread_rows<Real, 2, 1>), dim3(sgrid), dim3(kThreads), 0, s, aw, p, w, 2,

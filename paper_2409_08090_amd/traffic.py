@@ -27,7 +27,8 @@ from collections import defaultdict
 COPY_BYTES = 1 << 30
 STAGE_OF = [
     ("k_stats", "stats"), ("k_lowfreq", "lowfreq"), ("k_bins_sorted", "bin_sort"),
-    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_row_class", "row_class"),
+    ("k_sort", "bin_sort"), ("k_scan", "bin_sort"), ("k_row_flags", "row_class"),
+    ("k_row_compact", "row_class"),
     ("k_fft_last", "fft_last_power"), ("k_fft2_first", "fft_pass_0"),
     ("k_fft2_last", "fft_last_power"), ("k_fft2_out", "fft_out"),
 ]

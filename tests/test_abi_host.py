@@ -149,7 +149,10 @@ def _check_fft2_plan(d, prec):
     assert C == min(8, 16384 // L0) and C * L0 // 16 <= 1024 and 3 * L1 // 16 <= 1024, d
     lp = lambda L: L + L // 16 + 8  # noqa: E731
     assert d["first_lds_bytes"] == C * lp(L0) * 8 + _tw2(L0) * elem + L0 <= 163840, d
-    last = max(3 * lp(L1) * 8, 3 * (L1 // 2 if prec == "fp64" else L1) * elem) + _tw2(L1) * elem
+    if prec == "fp64":  # three grids side by side, exchanged and gathered in halves
+        last = max(3 * lp(L1) * 8, 3 * (L1 // 2) * elem) + _tw2(L1) * elem
+    else:  # the three grids one after another through one exchange line
+        last = lp(L1) * 8 + _tw2(L1) * elem
     assert d["last_lds_bytes"] == last <= 163840, d
 
 

@@ -10,9 +10,9 @@ def _step(scale=1.0):
         ("void mils::k_bins_sorted(mils::CallArgs, mils::Plan, mils::Work)", 2),
         ("void mils::k_lowfreq(mils::CallArgs, mils::Work)", 3),
         ("void mils::k_lowfreq_final(mils::CallArgs, mils::Work, int)", 1),
-        ("void mils::k_row_class<2>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_row_flags(mils::Plan, mils::Work, int, int)", 1),
         ("void mils::k_spread_rows<double, 2, 1>(mils::CallArgs, mils::Plan, mils::Work)", 5),
-        ("void mils::k_row_class<1>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_row_compact(mils::Plan, mils::Work, int)", 1),
         ("void mils::k_spread_rows<double, 1, 2>(mils::CallArgs, mils::Plan, mils::Work)", 7),
         ("void mils::k_fft_pass<double, 2048, 256, false>(...)", 11),   # first pass, 2f grid
         ("void mils::k_fft_pass<double, 2048, 256, false>(...)", 13),   # first pass, f grids
@@ -57,8 +57,8 @@ def test_two_pass_plan_stages():
     step = [
         ("void mils::k_stats(mils::CallArgs, mils::Work)", 1),
         ("void mils::k_bins_sorted(mils::CallArgs, mils::Plan, mils::Work)", 2),
-        ("void mils::k_row_class<1>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
-        ("void mils::k_row_class<2>(mils::Plan, mils::Work, int, unsigned char*, int*, int)", 1),
+        ("void mils::k_row_compact(mils::Plan, mils::Work, int)", 1),
+        ("void mils::k_row_flags(mils::Plan, mils::Work, int, int)", 1),
         ("void mils::k_spread_rows<double, 1, 2, false>(mils::CallArgs, mils::Plan, mils::Work)", 7),
         ("void mils::k_spread_rows<double, 2, 1, false>(mils::CallArgs, mils::Plan, mils::Work)", 5),
         ("void mils::k_fft2_first<double, 4096, 4, true>(...)", 30),
