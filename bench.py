@@ -216,16 +216,20 @@ def main():
     kname = "fft_last_power"
     k_ms = kernel_time(prec, power, kname, args.steps)
     k_bytes = 3.0 * plan["n"] * csize + 12.0 * c.nf
-    tr_total = tr_kernel = None
-    tpath = os.path.join(ROOT, "profiles", f"traffic_single_large_{prec}.json")
-    if os.path.exists(tpath):
+    def stored_traffic(pr):
+        """(bytes per periodogram, bytes of the last pass) from the counter
+        runs kept in profiles/, or (None, None) when absent or taken on other
+        kernel sources."""
+        tpath = os.path.join(ROOT, "profiles", f"traffic_single_large_{pr}.json")
         try:
             rec = json.load(open(tpath))
             if rec.get("kernel_hash") == trafficmod.kernel_source_hash(ROOT):
-                tr_total = float(sum(rec["bytes"].values()))
-                tr_kernel = rec["bytes"].get(kname)
+                return float(sum(rec["bytes"].values())), rec["bytes"].get(kname)
         except (OSError, ValueError, KeyError):
-            tr_total = tr_kernel = None
+            pass
+        return None, None
+
+    tr_total, tr_kernel = stored_traffic(prec)
     achieved = b_alg / (ms_per_step * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -274,6 +278,7 @@ def main():
             "alg_bytes": b32, "frac": round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "dense_frac": round(d32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "plan": {k: plan32[k] for k in ("n", "len", "width", "fft2")},
+            "traffic": stored_traffic("fp32")[0],
             "kernel": {"stage": kname, "avg_us": round(k32 * 1e3, 2),
                        "frac": round(kb32 / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "stages": stage_table("fp32", p32, args.steps, None)}

@@ -8,6 +8,10 @@ Runs (from the repository root, on the GPU):
     rocprofv3 --pmc WRITE_SIZE  ... same with -d <dir_write>
     python3 -m paper_2409_08090_amd.traffic <dir_fetch> <dir_write> > traffic.json
 
+and, for SQ_ counter runs (at most 8 SQ_ counters per run),
+
+    python3 -m paper_2409_08090_amd.traffic counters <dir> [<dir> ...] > counters.json
+
 FETCH_SIZE / WRITE_SIZE are read in KiB per dispatch.  Each is scaled by the
 ratio between the bytes a plain device copy of known size moves (read once,
 written once; bench.py --calibrate-copy runs one of 2^30 bytes) and what the
@@ -129,7 +133,78 @@ def kernel_source_hash(root):
     return h.hexdigest()[:16]
 
 
+def short_name(name):
+    """Kernel name without namespace, parameter list and the 'void ' prefix."""
+    n = name.strip('"')
+    if n.startswith("void "):
+        n = n[5:]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    return n.replace("mils::", "")
+
+
+def kernel_counters(dirs, cycles_per_ns=2.4, num_cu=256):
+    """Per kernel: dispatches, mean duration (ns) and the mean of every SQ_
+    counter per dispatch, over one or more rocprofv3 --pmc runs of the same
+    program; plus ratios that do not depend on the counters' units:
+    valu_busy = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES, lds_wait =
+    SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES, any_wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES,
+    bank_conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE, lds_util =
+    SQ_LDS_IDX_ACTIVE / (num_cu * duration cycles) (the share of the CUs' LDS
+    cycles spent on indexed accesses, against a peak of one access per CU
+    and cycle), and instructions per wave."""
+    acc = defaultdict(lambda: defaultdict(float))
+    cnt = defaultdict(lambda: defaultdict(int))
+    dur = defaultdict(list)
+    for d in dirs:
+        seen = set()
+        for r in _rows(d):
+            k = short_name(r["Kernel_Name"])
+            c = r["Counter_Name"].strip()
+            acc[k][c] += float(r["Counter_Value"])
+            key = (r["Dispatch_Id"], c)
+            if key not in seen:
+                seen.add(key)
+                cnt[k][c] += 1
+            if (r["Dispatch_Id"], "dur") not in seen:
+                seen.add((r["Dispatch_Id"], "dur"))
+                dur[k].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    out = {}
+    for k in acc:
+        m = {c: acc[k][c] / cnt[k][c] for c in acc[k]}
+        e = {"dispatches": max(cnt[k].values()), "mean_ns": sum(dur[k]) / len(dur[k])}
+        e.update(m)
+        wc = m.get("SQ_WAVE_CYCLES")
+        if wc:
+            for name, c in (("valu_busy", "SQ_ACTIVE_INST_VALU"), ("lds_wait", "SQ_WAIT_INST_LDS"),
+                            ("any_wait", "SQ_WAIT_ANY"), ("lds_busy", "SQ_ACTIVE_INST_LDS")):
+                if c in m:
+                    e[name] = m[c] / wc
+        if m.get("SQ_LDS_IDX_ACTIVE"):
+            if "SQ_LDS_BANK_CONFLICT" in m:
+                e["bank_conflict"] = m["SQ_LDS_BANK_CONFLICT"] / m["SQ_LDS_IDX_ACTIVE"]
+            e["lds_util"] = m["SQ_LDS_IDX_ACTIVE"] / (num_cu * e["mean_ns"] * cycles_per_ns)
+        if m.get("SQ_WAVES"):
+            for name, c in (("valu_per_wave", "SQ_INSTS_VALU"), ("lds_per_wave", "SQ_INSTS_LDS"),
+                            ("vmem_rd_per_wave", "SQ_INSTS_VMEM_RD")):
+                if c in m:
+                    e[name] = m[c] / m["SQ_WAVES"]
+        out[k] = e
+    return out
+
+
 def main(argv):
+    if len(argv) > 1 and argv[1] == "counters":
+        json.dump(kernel_counters(argv[2:]), sys.stdout, indent=1)
+        print()
+        return
     dfetch, dwrite = argv[1], argv[2]
     fetch = per_dispatch(dfetch, "FETCH_SIZE")
     write = per_dispatch(dwrite, "WRITE_SIZE")

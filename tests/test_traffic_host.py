@@ -70,3 +70,23 @@ def test_two_pass_plan_stages():
     want = {"stats": 1, "bin_sort": 2, "row_class": 2, "spread_f": 7, "spread_2f": 5,
             "fft_pass_0": 30, "lowfreq": 3, "fft_last_power": 40, "fft_out": 6}
     assert got == {k: float(v) for k, v in want.items()}
+
+
+def test_kernel_counters_summary(tmp_path):
+    hdr = ('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value","Start_Timestamp",'
+           '"End_Timestamp"\n')
+    rows = []
+    for did, (w, v, wc, la, bc) in enumerate([(4, 100, 1000, 50, 5), (4, 300, 3000, 150, 15)]):
+        name = '"void mils::k_fft2_last<double, 4096, 3, 4, true>(mils::Fft2Bufs<double>)"'
+        for cn, val in (("SQ_WAVES", w), ("SQ_INSTS_VALU", v), ("SQ_WAVE_CYCLES", wc),
+                        ("SQ_LDS_IDX_ACTIVE", la), ("SQ_LDS_BANK_CONFLICT", bc)):
+            rows.append(f'{did},{name},"{cn}",{val},1000,{1000 + 100 * (did + 1)}\n')
+    d = tmp_path / "run"
+    d.mkdir()
+    (d / "x_counter_collection.csv").write_text(hdr + "".join(rows))
+    got = traffic.kernel_counters([str(d)], cycles_per_ns=1.0, num_cu=1)
+    e = got["k_fft2_last<double, 4096, 3, 4, true>"]
+    assert e["dispatches"] == 2 and e["mean_ns"] == 150.0
+    assert e["SQ_INSTS_VALU"] == 200.0 and e["valu_per_wave"] == 50.0
+    assert abs(e["bank_conflict"] - 0.1) < 1e-12
+    assert abs(e["lds_util"] - 100.0 / 150.0) < 1e-12
