@@ -154,6 +154,15 @@ int mils_context_set_graphs(mils_context *ctx, int enable);
  * environment has MILS_FFT2=0 at context creation; the plans of both
  * choices are cached side by side. */
 int mils_context_set_fft2(mils_context *ctx, int enable);
+/* Batched periodograms (mils_periodogram_batch and the serving loop): a
+ * series whose three grids fit one workgroup's LDS (FP64 complex, at most
+ * 3072 cells) runs its whole pipeline -- statistics, direct sums near f = 0,
+ * spread, transforms, deconvolution and power -- in that workgroup, with no
+ * grid in device memory.  Its grids are FP64 in either precision.  On by
+ * default; 0 sends every series through the staged kernels. */
+int mils_context_set_batch_onchip(mils_context *ctx, int enable);
+/* Series of the last batch built on this context that ran on chip. */
+int64_t mils_context_batch_onchip(const mils_context *ctx);
 
 /* Fill *out with the plan for a periodogram of nd points with parameters p.
  * Host-only; valid on a host-only context. */

@@ -135,6 +135,9 @@ struct mils_context {
   // single-series calls may use the two-pass register-tile FFT (plans keyed
   // by this choice, so both kinds can coexist in the cache)
   bool fft2 = true;
+  // batched series whose grids fit one workgroup's LDS run on chip
+  bool batch_onchip = true;
+  int64_t last_batch_onchip = 0;  // such series in the last batch built
   int* host_status = nullptr;  // pinned
   DevStats* last_stats = nullptr;
   int64_t last_illposed = 0;  // ill-posed frequencies of the last call whose status was read
@@ -1077,6 +1080,27 @@ int mils_check_params(const mils_params* p, int64_t nd) {
   return rc != MILS_OK ? rc : check_params(p);
 }
 
+// Radix stages of the in-LDS transform of a series that runs on chip: radix
+// 16, 8, 4, 2, 5, 3 factors of n in ascending order (the largest stage last,
+// so that the stages' Ns stay at most n / R_last).  Returns the number of
+// stages, or 0 when n does not qualify (too large, not 5-smooth, too many
+// stages, an Ns above 1024 or more LDS than the cap).
+int small_radices(int64_t n, signed char* rad) {
+  if (n < 16 || n > kSmallMaxN || small_lds_bytes(n) > kSmallLdsCap) return 0;
+  int64_t m = n;
+  int cnt = 0;
+  for (int r : {16, 8, 4, 2, 5, 3}) {
+    while (m % r == 0 && cnt < kSmallMaxRad) {
+      rad[cnt++] = (signed char)r;
+      m /= r;
+    }
+  }
+  if (m != 1) return 0;
+  std::sort(rad, rad + cnt);
+  if (n / rad[cnt - 1] > 1024) return 0;
+  return cnt;
+}
+
 // Body of mils_periodogram_batch; the serving loop calls it with
 // use_graph = false (its batches change with every call).
 // Builds the launches of a batch in B: the series idx[0..m) (indices into the
@@ -1176,6 +1200,8 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     d.kzero = zero_index(d.f0, d.df, d.nf);
     d.plan = cls_of[c];
     d.index = (int)oc;
+    d.nsrad = ctx->batch_onchip ? small_radices(plans[cls_of[c]].n, d.srad) : 0;
+    d.small = d.nsrad > 0;
     wsz[c] = (layout_work(plans[cls_of[c]], d.nd, 3, nullptr, nullptr, true) + 255) & ~(size_t)255;
   }
   size_t cap = kBatchWorkspaceCap;
@@ -1199,13 +1225,19 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
   const int nchunks = (int)chunk_begin.size() - 1;
   // work items of every chunk
   struct ChunkItems {
-    std::vector<BatchItem> spread, pass[kMaxPass - 1], last;
+    std::vector<BatchItem> spread, pass[kMaxPass - 1], last, small;
+    size_t small_lds = 0;
   };
   std::vector<ChunkItems> ci(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     for (int64_t c = chunk_begin[k]; c < chunk_begin[k + 1]; ++c) {
       const Plan& q = plans[cls_of[c]];
       const int lc = (int)(c - chunk_begin[k]);
+      if (cur[c].small) {
+        ci[k].small.push_back({lc, 0});
+        ci[k].small_lds = std::max(ci[k].small_lds, small_lds_bytes(q.n));
+        continue;
+      }
       const int64_t ntl = (q.n + q.T - 1) / q.T;
       for (int64_t tl = 0; tl < ntl; ++tl) ci[k].spread.push_back({lc, (int)tl});
       for (int ip = 0; ip + 1 < q.npass; ++ip) {
@@ -1247,14 +1279,15 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
   std::vector<size_t> o_items(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     o_items[k] = off;
-    size_t cnt = ci[k].spread.size() + ci[k].last.size();
+    size_t cnt = ci[k].spread.size() + ci[k].last.size() + ci[k].small.size();
     for (int ip = 0; ip < kMaxPass - 1; ++ip) cnt += ci[k].pass[ip].size();
-    off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 1);
+    off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 2);
   }
   const size_t dev_bytes = off + 256;
   if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_max > ctx->budget)
     return fail(ctx, MILS_ERR_OOM, "batch workspace exceeds the HBM budget");
   he = hipStreamSynchronize(stream);
+  if (he == hipSuccess) he = batch_prepare();
   if (he != hipSuccess) return hip_fail(ctx, he, "batch setup");
   // room left by the budget for the batch's two buffers (0: no budget)
   const size_t room = ctx->budget ? ctx->budget - ctx->plan_bytes - ctx->ws_bytes : 0;
@@ -1307,6 +1340,7 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
   if (he == hipSuccess)
     he = hipMemcpy(B.dev + o_work, works.data(), sizeof(Work) * m, hipMemcpyHostToDevice);
   B.launches.assign(nchunks, BatchLaunch{});
+  ctx->last_batch_onchip = 0;
   for (int k = 0; k < nchunks && he == hipSuccess; ++k) {
     BatchLaunch& L = B.launches[k];
     const int64_t c0 = chunk_begin[k];
@@ -1345,6 +1379,10 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     L.last_items = put(ci[k].last);
     L.nlast = (int)ci[k].last.size();
     L.last_lds = last_lds;
+    L.small_items = put(ci[k].small);
+    L.nsmall = (int)ci[k].small.size();
+    L.small_lds = ci[k].small_lds;
+    ctx->last_batch_onchip += L.nsmall;
   }
   if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
   B.status_dev = reinterpret_cast<int*>(B.dev + o_st);
@@ -1504,6 +1542,7 @@ int mils_batch_run(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
   key = fnv1a(key, &common->flags, sizeof(uint32_t));
   key = fnv1a(key, sig.data(), sizeof(double) * ncurves);
   key = fnv1a(key, tmax.data(), sizeof(int) * ncurves);
+  key = fnv1a(key, &ctx->batch_onchip, sizeof(bool));
   const void* ptrs[4] = {t, y, dy, power};
   key = fnv1a(key, ptrs, sizeof(ptrs));
 
@@ -1583,6 +1622,16 @@ int mils_context_set_fft2(mils_context* ctx, int enable) {
   if (!ctx) return MILS_ERR_INVALID_ARG;
   ctx->fft2 = enable != 0;
   return MILS_OK;
+}
+
+int mils_context_set_batch_onchip(mils_context* ctx, int enable) {
+  if (!ctx) return MILS_ERR_INVALID_ARG;
+  ctx->batch_onchip = enable != 0;
+  return MILS_OK;
+}
+
+int64_t mils_context_batch_onchip(const mils_context* ctx) {
+  return ctx ? ctx->last_batch_onchip : 0;
 }
 
 int mils_context_set_graphs(mils_context* ctx, int enable) {

@@ -219,12 +219,14 @@ __device__ __forceinline__ void load_plan(const Plan* src, Plan* dst) {
   for (int i = threadIdx.x; i < (int)(sizeof(Plan) / sizeof(int)); i += blockDim.x) d[i] = s[i];
 }
 
-// Per-series prologue: one workgroup per series.
+// Per-series prologue: one workgroup per series (series that run in LDS
+// return at once).
 __global__ __launch_bounds__(NT) void k_bpro(BatchArgs ba) {
   __shared__ double sh[5 * NT];
   __shared__ int shi[2 * NT + 2];
   __shared__ Plan sp;
   const int ci = blockIdx.x;
+  if (ba.curves[ci].small) return;
   const BatchCurve c = ba.curves[ci];
   load_plan(ba.plans + c.plan, &sp);
   __syncthreads();
@@ -340,9 +342,123 @@ __global__ __launch_bounds__(last_threads<Real>()) void k_blast(BatchArgs ba,
                                                ba.inv_phihat[c.plan], st, smem, w.lowfix, 1);
 }
 
+// A series whose three grids fit LDS, whole in one workgroup: statistics and
+// direct sums near f = 0 as in the prologue; then each point adds its kernel
+// values straight into the LDS grids (FP64 atomics, no binning: any order of
+// the additions gives the same sums up to rounding) -- A and B at geometry f,
+// B2 at 2f; the three transforms in LDS; deconvolution, crop and power.  The
+// grids are FP64 in both precisions (the FP32 form keeps its plan, kernel
+// width and polynomial coefficients); nothing but the inputs and the power
+// crosses HBM.
+template <typename Real>
+__global__ __launch_bounds__(NT) void k_bsmall(BatchArgs ba, const BatchItem* items) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sh[5 * NT];
+  __shared__ int shi[2 * NT + 2];
+  __shared__ Plan sp;
+  __shared__ int rad[kSmallMaxRad];
+  const int tid = threadIdx.x;
+  const int ci = items[blockIdx.x].curve;
+  const BatchCurve c = ba.curves[ci];
+  load_plan(ba.plans + c.plan, &sp);
+  if (tid < c.nsrad) rad[tid] = c.srad[tid];
+  __syncthreads();
+  const CallArgs a = curve_args(ba, c);
+  const Work w = ba.works[ci];
+  stats_block(a, w.stats, sh, shi);
+  if (w.stats->status != 0) {
+    if (tid == 0) ba.status[c.index] = w.stats->status;
+    return;
+  }
+  lowfreq_block(a, w.stats, w.lowfix, sh);
+  const DevStats st = *w.stats;
+  const int n = (int)sp.n;
+  double2* g = reinterpret_cast<double2*>(smem);  // element l of grid q at 3 l + q
+  double2* twl = g + 3 * n;
+  for (int x = tid; x < 3 * n; x += NT) g[x] = make_double2(0.0, 0.0);
+  // two-level table of exp(2 pi i x / n): x < 64, then multiples of 64
+  for (int x = tid; x < 64 + (n + 63) / 64; x += NT) {
+    const int e = x < 64 ? x : (x - 64) * 64;
+    double sv, cv;
+    sincospi(2.0 * (double)e / (double)n, &sv, &cv);
+    twl[x] = make_double2(cv, sv);
+  }
+  __syncthreads();
+  constexpr int NC = sizeof(Real) == 8 ? kHornerN64 : kHornerN32;
+  const ConstPtr<Real> hc = (ConstPtr<Real>)(sp.hcoef);
+  const double tau = st.tau, invW = 1.0 / st.W, ysub = st.ysub;
+  const double nreal = (double)n, hw = sp.hw;
+  const int wd = sp.w;
+  for (int64_t j = tid; j < a.nd; j += NT) {
+    const double t = a.t[j];
+    double wj = 1.0;
+    if (a.dy) {
+      const double dv = a.dy[j];
+      wj = 1.0 / (dv * dv);
+    }
+    const double wh = wj * invW;
+    const double yt = a.y[j] - ysub;
+    double pc, ps;
+    prephase(t, tau, a.fch, a.fcl, pc, ps);
+#pragma unroll
+    for (int geo = 1; geo <= 2; ++geo) {
+      int cell;
+      double frac;
+      grid_coord32(t, tau, geo * a.df, nreal, n, cell, frac);
+      const int o0 = (int)ceil(frac - hw);
+      int lb = cell + o0;  // in (-w, n)
+      if (lb < 0) lb += n;
+      const Real u = (Real)(2.0 * ((double)o0 + hw - frac) - 1.0);
+      const double h0r = geo == 1 ? wh * yt * pc : wh * (pc * pc - ps * ps);
+      const double h0i = geo == 1 ? wh * yt * ps : wh * (2.0 * pc * ps);
+      const double h1r = wh * pc, h1i = wh * ps;
+      for (int kk = 0; kk < wd; ++kk) {
+        Real v = hc[kk];
+#pragma unroll
+        for (int jc = 1; jc < NC; ++jc) v = v * u + hc[jc * kHornerK + kk];
+        const double vv = (double)v;
+        int loc = lb + kk;
+        if (loc >= n) loc -= n;
+        if (geo == 1) {
+          atomicAdd(&g[3 * loc].x, vv * h0r);
+          atomicAdd(&g[3 * loc].y, vv * h0i);
+          atomicAdd(&g[3 * loc + 1].x, vv * h1r);
+          atomicAdd(&g[3 * loc + 1].y, vv * h1i);
+        } else {
+          atomicAdd(&g[3 * loc + 2].x, vv * h0r);
+          atomicAdd(&g[3 * loc + 2].y, vv * h0i);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<3 * kSmallMaxN, NT, true>(g, n, 3, 3, rad, c.nsrad, twl);
+  const int64_t nf = c.nf, K = c.K;
+  const double* iph = ba.inv_phihat[c.plan];
+  for (int64_t k = tid; k < nf; k += NT) {
+    const int64_t mm = k - K;
+    const int64_t m = mm < 0 ? mm + n : mm;
+    const double ip = iph[mm < 0 ? -mm : mm];
+    const double2 A = g[3 * m], B = g[3 * m + 1], B2 = g[3 * m + 2];
+    double s6[6] = {A.x * ip, A.y * ip, B.x * ip, B.y * ip, B2.x * ip, B2.y * ip};
+    const int64_t q = k - st.k_lo;
+    const bool low = q >= 0 && q < st.nlow;
+    if (low)
+      for (int jj = 0; jj < 6; ++jj) s6[jj] = w.lowfix[6 * q + jj];
+    double pw = ls_power(s6[0], s6[1], s6[2], s6[3], s6[4], s6[5], st, a.norm, a.fit_mean,
+                         low ? 0.0 : a.dmin);
+    if (k == a.kzero) pw = 0.0;
+    a.power[k] = pw;
+  }
+  if (tid == 0) ba.status[c.index] = 0;
+}
+
 template <typename Real>
 hipError_t launch_t(const BatchLaunch& bl, hipStream_t s) {
   const BatchArgs& ba = bl.args;
+  if (bl.nsmall > 0)
+    hipLaunchKernelGGL(k_bsmall<Real>, dim3(bl.nsmall), dim3(NT), bl.small_lds, s, ba,
+                       bl.small_items);
   hipLaunchKernelGGL(k_bpro, dim3(ba.ncurves), dim3(NT), 0, s, ba);
   if (bl.nspread > 0) {
     hipLaunchKernelGGL((k_bspread<Real, 1, 2>), dim3(bl.nspread), dim3(NT), 0, s, ba,
@@ -364,6 +480,16 @@ hipError_t launch_t(const BatchLaunch& bl, hipStream_t s) {
 
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
   return bl.prec == 1 ? launch_t<float>(bl, s) : launch_t<double>(bl, s);
+}
+
+hipError_t batch_prepare() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bsmall<double>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kSmallLdsCap);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bsmall<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsCap);
+  return e;
 }
 
 }  // namespace mils

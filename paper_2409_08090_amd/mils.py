@@ -141,6 +141,8 @@ SIGNATURES = {
     "mils_server_take": ([_P, ctypes.c_uint64, _P, ctypes.POINTER(mils_request_stats)],
                          ctypes.c_int),
     "mils_server_stats": ([_P, ctypes.POINTER(mils_server_counters)], ctypes.c_int),
+    "mils_context_set_batch_onchip": ([_P, ctypes.c_int], ctypes.c_int),
+    "mils_context_batch_onchip": ([_P], ctypes.c_int64),
     "mils_server_warm": ([_P, ctypes.POINTER(mils_params), ctypes.c_int64], ctypes.c_int),
     "mils_server_last_error": ([_P], ctypes.c_char_p),
     "mils_server_destroy": ([_P], ctypes.c_int),
@@ -204,6 +206,14 @@ class Context:
         """Allow (or not) the two-pass register-tile FFT for this context's
         single-series calls."""
         self.check(load().mils_context_set_fft2(self.handle, int(bool(enable))))
+
+    def set_batch_onchip(self, enable: bool):
+        """Batched series whose grids fit LDS run whole in one workgroup."""
+        self.check(load().mils_context_set_batch_onchip(self.handle, int(bool(enable))))
+
+    def batch_onchip(self) -> int:
+        """Series of the last batch built on this context that ran on chip."""
+        return int(load().mils_context_batch_onchip(self.handle))
 
     def set_graphs(self, enable: bool):
         """Graph replay of repeated single-series calls (on by default)."""

@@ -142,3 +142,30 @@ def test_autotuner_decides_per_band_and_keeps_parity(precision):
         assert worst <= TOL[precision]
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_onchip_and_staged_series_in_one_batch(precision):
+    """Small series (three grids in one workgroup's LDS) and larger ones in
+    the same batch: every series against the oracle, the on-chip series
+    against the staged kernels at every frequency, and the count of series
+    that ran on chip."""
+    rng = np.random.default_rng(21)
+    nds = [30, 57, 100, 120, 150, 199, 800, 2500, 64, 170, 3000, 90]
+    curves = [workloads.batch_curve(rng, nd) for nd in nds]
+    curves.append(workloads.uniform_series(5, 140, 1700))  # unequal weights, other grid
+    ctx = mils.Context(0)
+    on, st = run_batch(curves, precision, ctx=ctx)
+    n_on = ctx.batch_onchip()
+    ctx.set_batch_onchip(False)
+    off, st2 = run_batch(curves, precision, ctx=ctx)
+    assert ctx.batch_onchip() == 0
+    ctx.close()
+    assert np.all(st == 0) and np.all(st2 == 0)
+    assert 4 <= n_on < len(curves), n_on
+    rng = np.random.default_rng(1)
+    for c, p, q in zip(curves, on, off):
+        k = sample_k(c.nf, rng)
+        ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+        assert np.max(np.abs(p[k] - ref)) <= TOL[precision] * np.max(np.abs(ref)), c.nd
+        assert np.max(np.abs(p - q)) <= 2 * TOL[precision] * np.max(np.abs(q)), c.nd
