@@ -135,7 +135,7 @@ def kernel_source_hash(root):
 
 def short_name(name):
     """Kernel name without namespace, parameter list and the 'void ' prefix."""
-    n = name.strip('"')
+    n = name.strip('"').replace("(anonymous namespace)::", "")
     if n.startswith("void "):
         n = n[5:]
     depth = 0

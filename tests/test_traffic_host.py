@@ -90,3 +90,10 @@ def test_kernel_counters_summary(tmp_path):
     assert e["SQ_INSTS_VALU"] == 200.0 and e["valu_per_wave"] == 50.0
     assert abs(e["bank_conflict"] - 0.1) < 1e-12
     assert abs(e["lds_util"] - 100.0 / 150.0) < 1e-12
+
+
+def test_short_names():
+    assert traffic.short_name(
+        '"void mils::(anonymous namespace)::k_bpass<double>(mils::BatchArgs, int)"') == \
+        "k_bpass<double>"
+    assert traffic.short_name("mils::k_stats(mils::CallArgs, mils::Work)") == "k_stats"
