@@ -11,6 +11,8 @@
 // series has its own workspace.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "batch.h"
 #include "device_math.h"
 #include "fft_core.h"
@@ -483,12 +485,22 @@ hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
 }
 
 hipError_t batch_prepare() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bsmall<double>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)kSmallLdsCap);
+  // once per device (the serving loop's lanes build batches concurrently;
+  // later launches then never meet an attribute change)
+  static std::mutex mu;
+  static uint64_t done = 0;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done & bit)) return hipSuccess;
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bsmall<double>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsCap);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bsmall<float>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsCap);
+  if (e == hipSuccess) done |= bit;
   return e;
 }
 

@@ -11,6 +11,7 @@
 //                rescaling), crop to the requested modes and power assembly
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <type_traits>
@@ -696,7 +697,11 @@ __global__ __launch_bounds__(G * L1 / 16, G == 3 ? 3 : 2) void k_fft2_last(Fft2B
       int m1;
       if constexpr (G == 3) m1 = (i / PPT) * MR + tid + NT * (i % PPT);
       else m1 = t + TL * i;
-      ipv[i] = (G != 3 || (tid + NT * (i % PPT)) < MR) ? ip[m1] : 0.0;
+      // (factors of cropped modes are not read)
+      ipv[i] = (G != 3 || (tid + NT * (i % PPT)) < MR) &&
+                       fft2::crop(m0 + L0 * m1, pl.n, a.nf, pl.K) >= 0
+                   ? ip[m1]
+                   : 0.0;
     }
   }
   for (int x = tid; x < tw2_count(L1); x += NT) twl[x] = tw[ps.twL_off + x];
@@ -837,6 +842,13 @@ __global__ __launch_bounds__(256) void k_fft2_out(const V* __restrict__ res, V* 
   const int64_t bid = xcd_remap(blockIdx.x, (int64_t)gridDim.x);
   const int nt1 = L1 / TILE;
   const int64_t tm1 = bid % nt1, tm0 = bid / nt1;
+  // a tile whose modes all lie in the cropped band [nf - K, n - K) has
+  // nothing to move (its modes grow with m1 by L0 across the tile)
+  {
+    const int64_t lo = tm0 * TILE + (int64_t)L0 * (tm1 * TILE);
+    const int64_t hi = tm0 * TILE + TILE - 1 + (int64_t)L0 * (tm1 * TILE + TILE - 1);
+    if (lo >= nf - K && hi < n - K) return;
+  }
   const int tx = threadIdx.x % TILE, ty = threadIdx.x / TILE;
 #pragma unroll
   for (int r = 0; r < TILE; r += RS) {

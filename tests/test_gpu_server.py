@@ -56,7 +56,7 @@ def test_same_result_alone_and_in_a_mix():
     sizes = []
     for tk, c, prec in tickets:
         rc, p, st = result(srv, tk, c.nf)
-        assert rc == mils.MILS_OK
+        assert rc == mils.MILS_OK, (rc, c.nd, prec, srv.last_error(), srv.stats())
         sizes.append(st["batch_size"])
     for prec, c in probe.items():
         rc, p, st = result(srv, probe_tk[prec], c.nf)
