@@ -1243,7 +1243,10 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
       for (int ip = 0; ip + 1 < q.npass; ++ip) {
         const FftPass& ps = q.pass[ip];
         const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
-        for (int64_t x = 0; x < 3 * nblk; ++x) ci[k].pass[ip].push_back({lc, (int)x});
+        // one item per column block and grid, or per block for all three
+        const int per_item = prec == 1 ? kBatchPassGrids<float> : kBatchPassGrids<double>;
+        const int64_t nitems = nblk * (3 / per_item);
+        for (int64_t x = 0; x < nitems; ++x) ci[k].pass[ip].push_back({lc, (int)x});
       }
       const FftPass& ls = q.pass[q.npass - 1];
       for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x});

@@ -39,8 +39,9 @@ struct BatchCurve {
 };
 
 // A unit of work of a batched phase: series `curve` (index into curves),
-// and `sub`: the spreading tile, g * nblk + blk for a first/middle FFT pass,
-// or the row block of the last pass.
+// and `sub`: the spreading tile, the column block of a first/middle FFT pass
+// (FP64: all three grids; FP32: g * nblk + blk for grid g), or the row block
+// of the last pass.
 struct BatchItem {
   int curve;
   int sub;
@@ -61,6 +62,11 @@ struct BatchArgs {
   double dmin;  // power NaN where the fit's determinant is at most dmin
   int* status;                       // per series, caller order
 };
+
+// Grids per workgroup of a batched first/middle FFT pass: all three in FP64,
+// one in FP32 (its items are then g * nblk + blk).
+template <typename Real>
+constexpr int kBatchPassGrids = sizeof(Real) == 8 ? 3 : 1;
 
 // The launches of one batch (or of one chunk of it), in order.
 struct BatchLaunch {
