@@ -1234,22 +1234,22 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
       const Plan& q = plans[cls_of[c]];
       const int lc = (int)(c - chunk_begin[k]);
       if (cur[c].small) {
-        ci[k].small.push_back({lc, 0});
+        ci[k].small.push_back({lc, 0, cls_of[c]});
         ci[k].small_lds = std::max(ci[k].small_lds, small_lds_bytes(q.n));
         continue;
       }
       const int64_t ntl = (q.n + q.T - 1) / q.T;
-      for (int64_t tl = 0; tl < ntl; ++tl) ci[k].spread.push_back({lc, (int)tl});
+      for (int64_t tl = 0; tl < ntl; ++tl) ci[k].spread.push_back({lc, (int)tl, cls_of[c]});
       for (int ip = 0; ip + 1 < q.npass; ++ip) {
         const FftPass& ps = q.pass[ip];
         const int64_t nblk = ps.P * ((ps.S + ps.C - 1) / ps.C);
         // one item per column block and grid, or per block for all three
         const int per_item = prec == 1 ? kBatchPassGrids<float> : kBatchPassGrids<double>;
         const int64_t nitems = nblk * (3 / per_item);
-        for (int64_t x = 0; x < nitems; ++x) ci[k].pass[ip].push_back({lc, (int)x});
+        for (int64_t x = 0; x < nitems; ++x) ci[k].pass[ip].push_back({lc, (int)x, cls_of[c]});
       }
       const FftPass& ls = q.pass[q.npass - 1];
-      for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x});
+      for (int64_t x = 0; x < (ls.P + ls.C - 1) / ls.C; ++x) ci[k].last.push_back({lc, (int)x, cls_of[c]});
     }
   }
   // dynamic LDS of each pass launch (largest class that takes part)

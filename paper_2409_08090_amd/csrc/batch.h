@@ -45,6 +45,8 @@ struct BatchCurve {
 struct BatchItem {
   int curve;
   int sub;
+  int plan;  // the series' grid-size class (a copy of curves[curve].plan, so
+             // that the plan's parameters load beside the series' descriptors)
 };
 
 struct BatchArgs {

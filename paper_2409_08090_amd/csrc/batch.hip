@@ -268,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_bspread2(BatchArgs ba, const BatchItem* 
   const BatchItem it = items[blockIdx.x];
   const BatchCurve c = ba.curves[it.curve];
   const Work& w = ba.works[it.curve];
-  const Plan* pl = ba.plans + c.plan;
+  const Plan* pl = ba.plans + it.plan;
   // a tile is one row or part of one, or (short rows) several whole rows
   const int64_t a0 = (int64_t)it.sub * pl->T;
   const int64_t r0 = a0 / pl->S1;
@@ -306,16 +306,20 @@ __global__ __launch_bounds__(NT) void k_bpass(BatchArgs ba, const BatchItem* ite
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int EMID = sizeof(Real) == 8 ? kEmid64 : kEmid32;
   __shared__ FftPass ps;  // in LDS: its radix list is indexed at run time
+  __shared__ int bad;
   const BatchItem it = items[blockIdx.x];
   const Work& w = ba.works[it.curve];  // in place: grid[g] is indexed at run time
-  if (w.stats->status != 0) return;
-  const int cls = ba.curves[it.curve].plan;
+  const int cls = it.plan;
+  // the pass parameters and the series' status load side by side (both
+  // depend on the item only)
   {
     const int* src = reinterpret_cast<const int*>(&ba.plans[cls].pass[ip]);
     int* dst = reinterpret_cast<int*>(&ps);
     for (int i = threadIdx.x; i < (int)(sizeof(FftPass) / sizeof(int)); i += NT) dst[i] = src[i];
+    if (threadIdx.x == NT - 1) bad = w.stats->status != 0;
   }
   __syncthreads();
+  if (bad) return;
   constexpr int NGW = kBatchPassGrids<Real>;
   const int nblk = (int)(ps.P * ((ps.S + ps.C - 1) / ps.C));
   const int g0 = NGW == 3 ? 0 : it.sub / nblk;
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(last_threads<Real>()) void k_blast(BatchArgs ba,
   const DevStats st = *w.stats;
   if (st.status != 0) return;
   // no static LDS here: the dynamic part may use all 64 KB
-  const Plan* pl = ba.plans + c.plan;
+  const Plan* pl = ba.plans + it.plan;
   const int npass = pl->npass;
   const int64_t n = pl->n;
   const FftPass& ps = pl->pass[npass - 1];  // read in place (its radix list is indexed at run time)
@@ -359,8 +363,8 @@ __global__ __launch_bounds__(last_threads<Real>()) void k_blast(BatchArgs ba,
     b.rowflag[g] = nullptr;
   }
   fft_last_block<Real, 3, ELAST, last_threads<Real>()>(it.sub, b, ps, n, c.nf, c.K, a,
-                                               reinterpret_cast<const T2*>(ba.tw[c.plan]),
-                                               ba.inv_phihat[c.plan], st, smem, w.lowfix, 1);
+                                               reinterpret_cast<const T2*>(ba.tw[it.plan]),
+                                               ba.inv_phihat[it.plan], st, smem, w.lowfix, 1);
 }
 
 // A series whose three grids fit LDS, whole in one workgroup: statistics and
