@@ -129,7 +129,7 @@ def pct(a, q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard by frequency band across GPUs; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
