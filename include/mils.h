@@ -345,7 +345,14 @@ int mils_periodogram_batch(mils_context *ctx, int64_t ncurves, const int64_t *nd
  * (Sec. 1 of the paper sets the grid and the kernel width from eps; which
  * admissible pair is fastest depends on the size).  Returns MILS_OK with
  * *sigma and *tile_max set, or MILS_ERR_INVALID_ARG when the band has no
- * decision.  Setting MILS_AUTOTUNE=0 in the environment turns the tuner off. */
+ * decision.  Setting MILS_AUTOTUNE=0 in the environment turns the tuner off.
+ * With MILS_TUNE_CACHE naming a file when a context is created, the context
+ * reads the decisions recorded there for its device (architecture, CU count
+ * and memory size), and the tuner appends every new decision to it, so that
+ * later processes skip the tuning.
+ * Diagnostics: MILS_LOG_LEVEL (read when a context is created) = 1 writes
+ * every error to stderr, 2 also each plan built, each workspace growth and
+ * each tuning decision; 0 (the default) writes nothing. */
 int mils_batch_tuning(mils_context *ctx, int64_t nf, double eps, int32_t precision,
                       double *sigma, int32_t *tile_max);
 

@@ -9,7 +9,9 @@
 #include <cstddef>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstdarg>
 #include <map>
 #include <mutex>
 #include <string>
@@ -42,6 +44,42 @@ using PlanKey = std::tuple<int64_t, double, int, int, int64_t, int>;
 
 std::mutex g_err_mu;
 std::string g_create_err;
+
+// Diagnostics on stderr, by MILS_LOG_LEVEL (read at each context's
+// creation): 0 none (default), 1 errors, 2 also plans built, workspace
+// growth and tuning decisions.
+std::atomic<int> g_log_level{0};
+
+void read_log_level() {
+  const char* e = std::getenv("MILS_LOG_LEVEL");
+  g_log_level.store(e ? std::atoi(e) : 0);
+}
+
+// Batch tuning decisions persisted across processes: with MILS_TUNE_CACHE
+// naming a file, a context reads the decisions recorded there for its device
+// when it is created, and the autotuner appends each new decision.  One line
+// per decision: device key, N_f band, eps, precision, sigma, tile cap.  The
+// device key is the architecture name, the CU count and the memory size, so
+// that decisions of another GPU model are not reused.
+std::string tune_device_key(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "";
+  std::string arch(prop.gcnArchName);
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  return arch + ":" + std::to_string(prop.multiProcessorCount) + ":" +
+         std::to_string((unsigned long long)(prop.totalGlobalMem >> 30));
+}
+
+void mils_log(int level, const char* fmt, ...) {
+  if (g_log_level.load(std::memory_order_relaxed) < level) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[mils] %s\n", buf);
+}
 
 void host_dd_sum(double a, double b, double* s, double* e) {
   double x = a + b;
@@ -171,12 +209,52 @@ struct mils_context {
   } sg;
   // batch autotuner: (N_f band, eps, precision) -> (sigma, largest spreading tile)
   std::map<std::tuple<int, double, int>, std::pair<double, int>> tuned;
+  std::string tune_file;  // MILS_TUNE_CACHE at creation ("" = none)
+  std::string tune_key;   // this device's key in that file
 };
+
+namespace {
+
+// Reads the decisions recorded for this context's device (missing or
+// malformed lines are skipped).
+void load_tuning(mils_context* ctx) {
+  FILE* f = std::fopen(ctx->tune_file.c_str(), "r");
+  if (!f) return;
+  char key[256];
+  int band = 0, prec = 0, tile = 0;
+  double eps = 0.0, sigma = 0.0;
+  int loaded = 0;
+  while (std::fscanf(f, "%255s %d %lg %d %lg %d", key, &band, &eps, &prec, &sigma, &tile) == 6) {
+    if (ctx->tune_key != key) continue;
+    ctx->tuned[std::make_tuple(band, eps, prec)] = {sigma, tile};
+    ++loaded;
+  }
+  std::fclose(f);
+  mils_log(2, "tuning: %d decisions for %s from %s", loaded, ctx->tune_key.c_str(),
+           ctx->tune_file.c_str());
+}
+
+void save_tuning(mils_context* ctx, int band, double eps, int prec, double sigma, int tile) {
+  if (ctx->tune_file.empty()) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  FILE* f = std::fopen(ctx->tune_file.c_str(), "a");
+  if (!f) {
+    mils_log(1, "tuning cache %s cannot be written", ctx->tune_file.c_str());
+    return;
+  }
+  std::fprintf(f, "%s %d %.17g %d %.17g %d\n", ctx->tune_key.c_str(), band, eps, prec, sigma,
+               tile);
+  std::fclose(f);
+}
+
+}  // namespace
 
 namespace {
 
 int fail(mils_context* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
+  mils_log(1, "error %d: %s", code, msg.c_str());
   return code;
 }
 
@@ -185,6 +263,7 @@ int hip_fail(mils_context* ctx, hipError_t e, const char* where) {
     ctx->poisoned = true;
     ctx->err = std::string(where) + ": " + hipGetErrorString(e);
   }
+  mils_log(1, "device error in %s: %s (context unusable)", where, hipGetErrorString(e));
   return MILS_ERR_DEVICE;
 }
 
@@ -312,8 +391,12 @@ int get_plan(mils_context* ctx, int64_t nf, double eps, int prec, int G, PlanEnt
   slot = e;
   *out = &slot;
   ++ctx->plans_built;
-  ctx->plan_build_s +=
+  const double build_s =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_build).count();
+  ctx->plan_build_s += build_s;
+  mils_log(2, "plan nf=%lld eps=%g %s%s: n=%lld w=%d passes=%d%s, %.2f ms", (long long)nf, eps,
+           prec == 1 ? "fp32" : "fp64", batch ? " batch" : "", (long long)e.plan.n, e.plan.w,
+           e.plan.npass, e.plan.fft2 ? " two-pass" : "", build_s * 1e3);
   return MILS_OK;
 }
 
@@ -369,6 +452,7 @@ int ensure_workspace(mils_context* ctx, size_t bytes) {
   }
   ctx->ws = p;
   ctx->ws_bytes = got;
+  mils_log(2, "workspace grown to %.1f MB", (double)got / 1e6);
   // the statistics block holds the self-resetting reduction counter
   hipError_t he = hipMemset(p, 0, 4096);
   if (he != hipSuccess) return hip_fail(ctx, he, "workspace init");
@@ -593,6 +677,7 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
   c->device = device;
   c->budget = hbm_budget_bytes;
   c->fft2 = fft2_enabled();
+  read_log_level();
   if (device >= 0) {
     int count = 0;
     hipError_t he = hipGetDeviceCount(&count);
@@ -615,6 +700,12 @@ int mils_context_create(int device, uint64_t hbm_budget_bytes, mils_context** ou
       g_create_err = std::string("context init: ") + hipGetErrorString(he);
       delete c;
       return MILS_ERR_DEVICE;
+    }
+    if (const char* tf = std::getenv("MILS_TUNE_CACHE")) {
+      c->tune_file = tf;
+      c->tune_key = tune_device_key(device);
+      if (!c->tune_key.empty()) load_tuning(c);
+      else c->tune_file.clear();
     }
   }
   *out = c;
@@ -1479,6 +1570,9 @@ int autotune_batch(mils_context* ctx, int64_t ncurves, const int64_t* nd_off, co
     }
     if (rc != MILS_OK) break;
     ctx->tuned[key] = best;
+    mils_log(2, "tuning: band %d eps %g %s -> sigma %g, tile cap %d (%.3f ms)", kv.first,
+             common->eps, prec == 1 ? "fp32" : "fp64", best.first, best.second, best_ms);
+    save_tuning(ctx, kv.first, common->eps, prec, best.first, best.second);
   }
   (void)hipStreamSynchronize(stream);
   free_batch_state(T);

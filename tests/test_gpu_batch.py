@@ -169,3 +169,34 @@ def test_onchip_and_staged_series_in_one_batch(precision):
         ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
         assert np.max(np.abs(p[k] - ref)) <= TOL[precision] * np.max(np.abs(ref)), c.nd
         assert np.max(np.abs(p - q)) <= 2 * TOL[precision] * np.max(np.abs(q)), c.nd
+
+
+def test_tuning_cache_persists_decisions(tmp_path, monkeypatch):
+    """With MILS_TUNE_CACHE naming a file, the autotuner's decisions are
+    appended there and a new context for the same device reads them at
+    creation (before any batch of its own)."""
+    path = tmp_path / "tuning.txt"
+    monkeypatch.setenv("MILS_TUNE_CACHE", str(path))
+    rng = np.random.default_rng(23)
+    curves = [workloads.batch_curve(rng, int(n)) for n in rng.integers(1500, 1700, 40)]
+    ctx = mils.Context(0)
+    try:
+        _, st = run_batch(curves, "fp64", ctx=ctx)
+        assert np.all(st == 0)
+        dec = ctx.batch_tuning(curves[0].nf, EPS["fp64"], "fp64")
+    finally:
+        ctx.close()
+    assert dec is not None
+    lines = path.read_text().split("\n")
+    assert any(len(x.split()) == 6 for x in lines), lines
+    fresh = mils.Context(0)
+    try:
+        assert fresh.batch_tuning(curves[0].nf, EPS["fp64"], "fp64") == dec
+    finally:
+        fresh.close()
+    monkeypatch.delenv("MILS_TUNE_CACHE")
+    plain = mils.Context(0)
+    try:
+        assert plain.batch_tuning(curves[0].nf, EPS["fp64"], "fp64") is None
+    finally:
+        plain.close()
