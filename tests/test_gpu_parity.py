@@ -570,3 +570,26 @@ def test_illposed_frequencies_are_nan_and_counted(precision):
     mils.periodogram(dev(c.t), dev(c.y), dev(c.dy), c.f0, c.df, c.nf, ctx=ctx)
     assert mils.context_illposed(ctx) == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nf,shift", [(12000, 1), (12001, 7), (12000, 5999), (240001, 1),
+                                      (3_000_000, 3)])
+def test_subgrid_is_a_suffix(precision, nf, shift):
+    """The grid (f0 + s df, N_f - s) gives the last N_f - s values of
+    (f0, N_f): the two calls have different grid sizes, centring and crop,
+    so off-by-ones in any of them show; the shorter call is also checked
+    against the oracle at its band edges."""
+    c = workloads.single_small(seed=9, nd=max(1000, nf // 12))
+    t, y, dy = dev(c.t), dev(c.y), dev(c.dy)
+    eps = EPS[precision]
+    a = mils.periodogram(t, y, dy, c.f0, c.df, nf, eps=eps, precision=precision).cpu().numpy()
+    f0s = c.f0 + shift * c.df
+    b = mils.periodogram(t, y, dy, f0s, c.df, nf - shift, eps=eps,
+                         precision=precision).cpu().numpy()
+    err = rel_err(b, a[shift:])
+    k = np.concatenate([np.arange(20), np.arange(nf - shift - 20, nf - shift)])
+    ref = oracle.periodogram(c.t, c.y, c.dy, f0s, c.df, k=k)
+    print(f"[suffix {precision} nf={nf} s={shift}] {err:.2e}", flush=True)
+    assert err <= TOL[precision]
+    assert rel_err(b[k], ref) <= TOL[precision]

@@ -276,3 +276,17 @@ def test_time_and_frequency_rescaling():
     a = oracle.periodogram(t, y, dy, 0.002, 0.017, nf=40)
     b = oracle.periodogram(4.0 * t, y, dy, 0.002 / 4, 0.017 / 4, nf=40)
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+@settings(max_examples=20, deadline=None)
+@given(series, st.integers(1, 30))
+def test_subgrid_is_a_suffix(s, shift):
+    """The grid (f0 + s df, N_f - s) gives the last N_f - s values of the grid
+    (f0, N_f): catches off-by-ones in frequency indexing (its binary64
+    frequencies differ only by the rounding of f0 + s df)."""
+    n, seed = s
+    _, t, y, dy = _series(n, seed)
+    f0, df, nf = 0.002, 0.0137, 41
+    a = oracle.periodogram(t, y, dy, f0, df, nf=nf)
+    b = oracle.periodogram(t, y, dy, f0 + shift * df, df, nf=nf - shift)
+    np.testing.assert_allclose(b, a[shift:], rtol=1e-9, atol=1e-12)
