@@ -180,6 +180,16 @@ int mils_plan_info(mils_context *ctx, int64_t nd, const mils_params *p, mils_pla
 int mils_kernel_table(mils_context *ctx, const mils_params *p, double *coef, int32_t *ncoef,
                       int32_t *kmax, int32_t *width, double *beta);
 
+/* The deconvolution factors 1 / phihat(m) of the single-series plan of p
+ * (host-only): phihat(m) = w int_0^1 phi(z) cos(pi w m z / n) dz, the
+ * Fourier transform of the spreading kernel at mode m of the n-cell grid
+ * (Sec. 1, Eq. 2: the diagonal rescaling after the FFT), by the plan's
+ * Gauss-Legendre rule (2w + 16 nodes), the rule and sum the device's table
+ * uses (there in FP64).  modes: count values in [0, floor(nf / 2)] (host);
+ * inv_phihat: count doubles (host, caller-owned); *n_grid: the plan's n. */
+int mils_kernel_transform(mils_context *ctx, const mils_params *p, int64_t count,
+                          const int64_t *modes, double *inv_phihat, int64_t *n_grid);
+
 /* Check the arguments of mils_periodogram without touching the device;
  * returns MILS_OK or the code mils_periodogram would return before launching. */
 int mils_check_periodogram_args(const double *t, const double *y, int64_t nd,

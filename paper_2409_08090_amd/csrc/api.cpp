@@ -812,6 +812,31 @@ int mils_kernel_table(mils_context* ctx, const mils_params* p, double* coef, int
   return MILS_OK;
 }
 
+int mils_kernel_transform(mils_context* ctx, const mils_params* p, int64_t count,
+                          const int64_t* modes, double* inv_phihat, int64_t* n_grid) {
+  if (!ctx || (count > 0 && (!modes || !inv_phihat)) || count < 0 || !n_grid)
+    return MILS_ERR_INVALID_ARG;
+  int rc = check_params(p);
+  if (rc != MILS_OK) return fail(ctx, rc, "invalid plan query");
+  PlanEntry* pe = nullptr;
+  rc = get_plan(ctx, p->nf, p->eps, p->precision, 3, &pe, false, false, 0, 0, ctx->fft2);
+  if (rc != MILS_OK) return rc;
+  const Plan& pl = pe->plan;
+  std::vector<double> z, gphi;
+  phihat_nodes(pl, &z, &gphi);
+  *n_grid = pl.n;
+  for (int64_t i = 0; i < count; ++i) {
+    if (modes[i] < 0 || modes[i] > pl.K) return fail(ctx, MILS_ERR_INVALID_ARG, "mode out of range");
+    // the device table's sum (k_phihat), accumulated here in long double
+    const long double alpha = (long double)modes[i] * (3.14159265358979323846264338327950288L *
+                                                      (long double)pl.w / (long double)pl.n);
+    long double sum = 0.0L;
+    for (size_t r = 0; r < z.size(); ++r) sum += (long double)gphi[r] * cosl(alpha * z[r]);
+    inv_phihat[i] = (double)(1.0L / ((long double)pl.w * sum));
+  }
+  return MILS_OK;
+}
+
 int mils_trig_sums(mils_context* ctx, const double* t, const double* h, int64_t nd, double f0,
                    double df, int64_t nf, double eps, int32_t precision, double* out,
                    void* hip_stream) {

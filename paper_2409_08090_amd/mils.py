@@ -103,6 +103,8 @@ SIGNATURES = {
     "mils_batch_tuning": ([_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)],
                           ctypes.c_int),
+    "mils_kernel_transform": ([_P, ctypes.POINTER(mils_params), ctypes.c_int64, _P, _P,
+                               ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "mils_kernel_table": ([_P, ctypes.POINTER(mils_params), _P, ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                            ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -292,6 +294,24 @@ def kernel_table(nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01):
                                     ctypes.byref(km), ctypes.byref(wd), ctypes.byref(be)))
     ctx.close()
     return buf[: nc.value * km.value].reshape(nc.value, km.value).copy(), wd.value, be.value
+
+
+def kernel_transform(nf, modes, eps=1e-9, precision="fp64"):
+    """(1 / phihat(m) for each mode m, grid size n) of the plan of nf
+    frequencies (host only, no GPU needed)."""
+    import numpy as np
+    lib = load()
+    ctx = Context(-1)
+    p = make_params(0.01, 0.01, nf, eps, precision)
+    m = np.ascontiguousarray(modes, dtype=np.int64)
+    out = np.empty(m.size)
+    n = ctypes.c_int64()
+    try:
+        ctx.check(lib.mils_kernel_transform(ctx.handle, ctypes.byref(p), m.size, m.ctypes.data,
+                                            out.ctypes.data, ctypes.byref(n)))
+    finally:
+        ctx.close()
+    return out, int(n.value)
 
 
 def plan_info(nd, nf, eps=1e-9, precision="fp64", f0=0.01, df=0.01) -> dict:

@@ -277,3 +277,32 @@ def test_batch_tuning_query_without_a_decision():
     sg, tm = C.c_double(), C.c_int32()
     assert lib.mils_batch_tuning(ctx.handle, 0, 1e-9, 0, C.byref(sg), C.byref(tm)) == mils.MILS_ERR_INVALID_ARG
     ctx.close()
+
+
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+@pytest.mark.parametrize("nf,eps,prec", [(12_000, 1e-9, "fp64"), (12_000_000, 1e-9, "fp64"),
+                                         (100_000, 1e-12, "fp64"), (12_000_000, 1e-5, "fp32"),
+                                         (7, 1e-9, "fp64")])
+def test_kernel_transform_matches_adaptive_quadrature(nf, eps, prec):
+    # 1/phihat(m) = 1 / (w int_0^1 phi(z) cos(pi w m z / n) dz) by the plan's
+    # Gauss-Legendre rule, against scipy's adaptive quadrature of the same
+    # integral (an independent rule): the deconvolution of Sec. 1, Eq. 2.
+    from scipy import integrate
+    K = nf // 2
+    modes = np.unique(np.array([0, 1, 2, K // 3, K // 2, max(K - 1, 0), K], dtype=np.int64))
+    inv, n = mils.kernel_transform(nf, modes, eps, prec)
+    _, w, beta = mils.kernel_table(nf, eps, prec)
+    phat0 = None
+    for m, v in zip(modes, inv):
+        a = math.pi * w * m / n
+        f = lambda z: math.exp(beta * (math.sqrt(max(1.0 - z * z, 0.0)) - 1.0)) * math.cos(a * z)  # noqa: E731
+        val, _ = integrate.quad(f, 0.0, 1.0, limit=400, epsabs=1e-300, epsrel=1e-12)
+        ref = w * val  # phihat(m)
+        phat0 = ref if m == 0 else phat0
+        # the rule's error comes from the kink of phi at z = 1 (size exp(-beta)),
+        # relative to phihat(0): 1e-12 for the FP64 plans, ~1e-10 for the FP32
+        # plan's narrow kernel
+        bound = (1e-12 + 1e-3 * math.exp(-beta)) * phat0
+        assert abs(1.0 / v - ref) <= bound, (m, 1.0 / v, ref, bound)
+    # the deconvolution grows towards the band edge (the kernel's transform decays)
+    assert np.all(np.diff(inv) > 0)
