@@ -254,6 +254,9 @@ namespace {
 
 int fail(mils_context* ctx, int code, const std::string& msg) {
   if (ctx) ctx->err = msg;
+  // a handled failure (a refused allocation, say) must not stay the thread's
+  // last HIP error, or a later launch check would report it
+  (void)hipGetLastError();
   mils_log(1, "error %d: %s", code, msg.c_str());
   return code;
 }

@@ -500,6 +500,7 @@ hipError_t launch_t(const BatchLaunch& bl, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_batch(const BatchLaunch& bl, hipStream_t s) {
+  (void)hipGetLastError();  // see launch_path: a handled earlier failure is not this launch's
   return bl.prec == 1 ? launch_t<float>(bl, s) : launch_t<double>(bl, s);
 }
 

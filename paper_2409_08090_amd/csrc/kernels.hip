@@ -1007,10 +1007,13 @@ static void big_lds(const void* kern, size_t bytes) {
   if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
       hipSuccess)
     have = bytes;
+  else
+    (void)hipGetLastError();  // the launch then reports the refusal itself
 }
 
 hipError_t launch_phihat2(double* iphi2, const double* inv_phihat, int L0, int L1, int64_t n,
                           int64_t nf, int64_t K, hipStream_t s) {
+  (void)hipGetLastError();
   hipLaunchKernelGGL(k_phihat2, dim3(grid_for(n, 1 << 30)), dim3(kThreads), 0, s, iphi2,
                      inv_phihat, L0, L1, n, nf, K);
   return hipGetLastError();
@@ -1018,6 +1021,7 @@ hipError_t launch_phihat2(double* iphi2, const double* inv_phihat, int L0, int L
 
 hipError_t launch_phihat(double* inv_phihat, int64_t K, double w, double n, const double* z,
                          const double* gphi, int q, hipStream_t s) {
+  (void)hipGetLastError();
   hipLaunchKernelGGL(k_phihat, dim3(grid_for(K + 1, 1 << 30)), dim3(kThreads), 0, s, inv_phihat,
                      K, w, n, z, gphi, q);
   return hipGetLastError();
@@ -1430,8 +1434,13 @@ static hipError_t launch_path_t(const CallArgs& a, const Plan& p, const Work& w,
   return hipGetLastError();
 }
 
+// Every launch sequence below reports hipGetLastError() after its launches;
+// it first discards the calling thread's last error, which an earlier,
+// already handled failure (a refused allocation) may have left set and
+// which would otherwise be taken for a failed launch.
 hipError_t launch_path(const CallArgs& a, const Plan& p, const Work& w, hipStream_t s,
                        const StageHook* hook, const AuxStream* aux) {
+  (void)hipGetLastError();
   if (p.prec == 1) return launch_path_t<float>(a, p, w, s, hook, aux);
   return launch_path_t<double>(a, p, w, s, hook, aux);
 }
@@ -1513,6 +1522,7 @@ static hipError_t launch_series_group_t(const CallArgs& a, const Plan& p, const 
 
 hipError_t launch_weight_sums(const CallArgs& aw, const Plan& p, const Work& w, double* bsum_b,
                               double* bsum_b2, hipStream_t s) {
+  (void)hipGetLastError();
   if (p.prec == 1) return launch_weight_sums_t<float>(aw, p, w, bsum_b, bsum_b2, s);
   return launch_weight_sums_t<double>(aw, p, w, bsum_b, bsum_b2, s);
 }
@@ -1520,11 +1530,13 @@ hipError_t launch_weight_sums(const CallArgs& aw, const Plan& p, const Work& w, 
 hipError_t launch_series_group(const CallArgs& a, const Plan& p, const Work& w,
                                const SeriesGroup& sg, hipStream_t s) {
   if (sg.m < 1 || sg.m > 3) return hipErrorInvalidValue;
+  (void)hipGetLastError();
   if (p.prec == 1) return launch_series_group_t<float>(a, p, w, sg, s);
   return launch_series_group_t<double>(a, p, w, sg, s);
 }
 
 hipError_t launch_direct(const CallArgs& a, const Work& w, hipStream_t s) {
+  (void)hipGetLastError();
   enqueue_stats(a, w, s);
   const int64_t per = (int64_t)kDirThreads * kDirF;
   const int64_t nb = (a.nf + per - 1) / per;

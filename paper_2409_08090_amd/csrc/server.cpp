@@ -108,7 +108,10 @@ bool grow_pinned(double** p, size_t* cap, size_t need) {
   *p = nullptr;
   *cap = 0;
   size_t c = std::max(need, (size_t)(1 << 20));
-  if (hipHostMalloc(reinterpret_cast<void**>(p), c * sizeof(double)) != hipSuccess) return false;
+  if (hipHostMalloc(reinterpret_cast<void**>(p), c * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
   *cap = c;
   return true;
 }
