@@ -9,10 +9,14 @@
 // not fit the 160 KB of LDS.  So each thread keeps 16 elements in registers
 // and the LDS only carries the exchange between radix-16 stages, one half
 // (real or imaginary parts) at a time when a whole tile would not fit.  The
-// first pass stores its tile contiguously (the last pass then reads 64-byte
-// pieces of each row); the last pass holds one row per workgroup, so its
-// results are written row by row and transposed by a separate tiled kernel
-// (scattered 8-byte stores of the power cost more than the transpose).
+// first pass writes its result row-major, a piece of C elements of each row
+// per workgroup, so that the last pass reads whole rows contiguously (the
+// other way round -- column blocks stored contiguously, the last pass reading
+// 64-byte pieces -- made the last pass, which has one workgroup per CU and
+// waits for its loads, 426 us instead of 328 at 4096 x 4096 in FP64); the
+// last pass holds one row per workgroup, so its results are written row by
+// row and transposed by a separate tiled kernel (scattered 8-byte stores of
+// the power cost more than the transpose).
 #pragma once
 
 #include "fft2_index.h"
@@ -128,7 +132,7 @@ __device__ __forceinline__ constexpr int f2_reg_of(int j) {
 template <typename Real>
 struct Fft2Bufs {
   typename cplx<Real>::T* grid[3];  // natural layout [L0][L1]
-  typename cplx<Real>::T* mid[3];   // column blocks [L1/C][L0][C] (a buffer of its own)
+  typename cplx<Real>::T* mid[3];   // first-pass result [L0][L1] (a buffer of its own)
   const unsigned char* rowflag[3];  // active rows of each grid's geometry
 };
 

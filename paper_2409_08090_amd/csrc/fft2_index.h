@@ -4,8 +4,9 @@
 // A grid of n = L0 * L1 cells, cell l = l0 * L1 + s (row l0 < L0, column
 // s < L1), is transformed (sign +, unnormalised) in two passes:
 //   first pass: length-L0 transforms down each column s, output digit m0,
-//     multiplied by exp(2 pi i s m0 / n), stored as column blocks of C
-//     columns: element (s, m0) at (s / C) * (L0 C) + m0 C + s mod C;
+//     multiplied by exp(2 pi i s m0 / n), stored row-major: element
+//     (s, m0) at m0 * L1 + s (a workgroup of C columns writes C-element
+//     pieces of every row);
 //   last pass: length-L1 transforms along each row m0 of that result,
 //     output digit m1; mode m = m0 + L0 m1.
 // Each transform of length L = 16^k f (f in {1, 2, 4, 8}) is held in the

@@ -594,9 +594,11 @@ __global__ __launch_bounds__(kThreads) void k_phihat2(double* iphi2, const doubl
 // Two-pass register-tile FFT (fft2.h).
 // ============================================================================
 // First pass: the C columns s0 .. s0+C-1 of grid blockIdx.y; the rows whose
-// flag is clear are zero and are not read.  Output: the column block stored
-// contiguously, element (s, m0) at (s / C) L0 C + m0 C + s mod C, multiplied
-// by exp(2 pi i s m0 / n).
+// flag is clear are zero and are not read.  Output: row-major [L0][L1],
+// element (s, m0) at m0 L1 + s, multiplied by exp(2 pi i s m0 / n): the
+// workgroup writes a C-element piece of every row (neighbouring column
+// blocks run on one XCD, whose L2 joins their pieces), so that the last pass
+// reads whole rows contiguously.
 template <typename Real, int L0, int C, bool HALVES>
 __global__ __launch_bounds__(C * L0 / 16, 4) void k_fft2_first(Fft2Bufs<Real> b, FftPass ps,
                                                              const typename cplx<Real>::T* tw,
@@ -639,17 +641,17 @@ __global__ __launch_bounds__(C * L0 / 16, 4) void k_fft2_first(Fft2Bufs<Real> b,
   const T2 w0 = cmul(thi[q0 >> ps.bshift], tlo[q0 & mask]);
   const T2 ws = cmul(thi[qs >> ps.bshift], tlo[qs & mask]);
   f2_line<L0, HALVES>(v, t, ex + c * LP, twl);
-  T2* out = b.mid[g] + sb * (int64_t)(L0 * C) + c;
+  T2* out = b.mid[g] + s;
   T2 tk = w0;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    out[(int64_t)(t + TL * j) * C] = cmul(v[f2_reg_of<L0>(j)], tk);
+    out[(int64_t)(t + TL * j) * L1] = cmul(v[f2_reg_of<L0>(j)], tk);
     tk = cmul(tk, ws);
   }
 }
 
-// Last pass: row m0 of each of the G grids (threads g * TL + t), read from
-// the column blocks in pieces of C elements.  G = 3: the grid-0 threads take
+// Last pass: row m0 of each of the G grids (threads g * TL + t), read
+// contiguously.  G = 3: the grid-0 threads take
 // B and B2 of their outputs from the other grids' threads (through LDS) and
 // write the power of mode m = m0 + L0 m1 to out[m0 L1 + m1]; G = 1: the
 // deconvolved sums (double2).  Cropped modes are not written.
@@ -681,12 +683,9 @@ __global__ __launch_bounds__(G * L1 / 16, G == 3 ? 3 : 2) void k_fft2_last(Fft2B
   Lds* ex = reinterpret_cast<Lds*>(smem);
   T2* twl = reinterpret_cast<T2*>(smem + (exb > cbb ? exb : cbb));
   T2 v[16];
-  const T2* in = b.mid[g] + m0 * C;
+  const T2* in = b.mid[g] + m0 * L1;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int sc = t + q * TL;
-    v[q] = in[(int64_t)(sc / C) * (L0 * C) + (sc & (C - 1))];
-  }
+  for (int q = 0; q < 16; ++q) v[q] = in[t + q * TL];
   // the kernel-transform factors of the outputs this thread finishes
   constexpr int NIP = G == 3 ? NR * PPT : 16;
   double ipv[NIP];
@@ -784,12 +783,9 @@ __global__ __launch_bounds__(L1 / 16, sizeof(Real) == 8 ? 1 : 2) void k_fft2_las
   T2* twl = reinterpret_cast<T2*>(smem + (size_t)LP * sizeof(Lds));
   T2 va[16], vb[16], vc[16];
   auto load = [&](T2(&v)[16], int g) {
-    const T2* in = b.mid[g] + m0 * C;
+    const T2* in = b.mid[g] + m0 * L1;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int sc = t + q * TL;
-      v[q] = in[(int64_t)(sc / C) * (L0 * C) + (sc & (C - 1))];
-    }
+    for (int q = 0; q < 16; ++q) v[q] = in[t + q * TL];
   };
   load(va, 0);
   load(vb, 1);

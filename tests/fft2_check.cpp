@@ -83,7 +83,7 @@ int main(int argc, char** argv) {
   std::normal_distribution<double> nd(0.0, 1.0);
   std::vector<cd> x(n), mid(n), X(n, cd(NAN, NAN));
   for (auto& e : x) e = cd(nd(rng), nd(rng));
-  // first pass: column blocks of C columns
+  // first pass: column blocks of C columns, results stored row-major [L0][L1]
   {
     const int TL = threads(L0);
     std::vector<cd> lds((size_t)C * line_pitch(L0));
@@ -101,7 +101,7 @@ int main(int argc, char** argv) {
           for (int r = 0; r < 16; ++r) {
             const int m0 = t + TL * final_j(L0, r);
             const cd w = root((long double)(s0 + c) * m0, (long double)n);
-            mid[(int64_t)sb * L0 * C + (int64_t)m0 * C + c] = v[t][r] * w;
+            mid[(int64_t)m0 * L1 + s0 + c] = v[t][r] * w;
           }
       }
     }
@@ -117,7 +117,7 @@ int main(int argc, char** argv) {
       for (int t = 0; t < TL; ++t)
         for (int q = 0; q < 16; ++q) {
           const int s = t + q * TL;
-          v[t][q] = mid[(int64_t)(s / C) * L0 * C + (int64_t)m0 * C + s % C];
+          v[t][q] = mid[(int64_t)m0 * L1 + s];
         }
       run_line_stages(L1, TL, v, lds, stamp, 0, epoch);
       if (fails) return 1;
