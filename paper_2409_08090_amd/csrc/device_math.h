@@ -125,6 +125,26 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// Streaming (nontemporal) loads and stores, for data read or written once:
+// marked so that the caches do not keep them in place of data that is used
+// again.
+typedef double d2v_t __attribute__((ext_vector_type(2)));
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const d2v_t w = __builtin_nontemporal_load(reinterpret_cast<const d2v_t*>(p));
+  return make_double2(w.x, w.y);
+}
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+  const f2v_t w = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));
+  return make_float2(w.x, w.y);
+}
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  const d2v_t w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<d2v_t*>(p));
+}
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }

@@ -140,7 +140,7 @@ struct Fft2Bufs {
 // of L0 and the row flags.
 template <typename Real>
 __host__ __device__ constexpr size_t f2_first_lds(int L0, int C, bool halves) {
-  return (size_t)C * fft2::line_pitch(L0) * (halves ? sizeof(Real) : 2 * sizeof(Real)) +
+  return (size_t)C * fft2::line_pitch_c(L0, C) * (halves ? sizeof(Real) : 2 * sizeof(Real)) +
          (size_t)tw2_count(L0) * 2 * sizeof(Real) + (size_t)L0;
 }
 // LDS bytes of a last-pass workgroup: the exchange lines (reused for the

@@ -69,6 +69,11 @@ F2_HD constexpr int pad(int p) { return p + (p >> 4); }
 // LDS elements per line (pads, plus 8 so that consecutive lines start on
 // different banks)
 F2_HD constexpr int line_pitch(int L) { return L + L / 16 + 8; }
+// pitch of the C lines of a first-pass workgroup, whose lanes take the C
+// columns fastest: with lines 16 / C elements apart modulo 16, the 16 lanes
+// of one LDS access cycle (C columns x 16 / C threads, 8-byte elements) fall
+// on distinct bank pairs
+F2_HD constexpr int line_pitch_c(int L, int C) { return L + L / 16 + (C >= 2 ? 16 / C : 8); }
 
 // output index (0 .. nf-1) of mode m of an n-cell grid, or -1 when cropped:
 // modes m <= nf-1-K are the non-negative ones, m >= n-K the negative ones

@@ -56,7 +56,7 @@ static void run_line_stages(int L, int nthreads_line, std::vector<std::vector<cd
         for (int q = 0; q < R; ++q) {
           const int p = out_pos(L, s, t + TL * k, q);
           const int slot = base + pad(p);
-          CHECK(p >= 0 && p < L && slot >= base && slot < base + line_pitch(L), "write slot L=%d s=%d p=%d", L, s, p);
+          CHECK(p >= 0 && p < L && slot >= base && slot < base + L + L / 16, "write slot L=%d s=%d p=%d", L, s, p);
           CHECK(stamp[slot] != epoch, "slot written twice L=%d s=%d p=%d", L, s, p);
           lds[slot] = v[t][reg(L, s, k, q)];
           stamp[slot] = epoch;
@@ -67,11 +67,42 @@ static void run_line_stages(int L, int nthreads_line, std::vector<std::vector<cd
         for (int q = 0; q < R2; ++q) {
           const int p = in_pos(L, s + 1, t + TL * k, q);
           const int slot = base + pad(p);
-          CHECK(p >= 0 && p < L && slot < base + line_pitch(L), "read slot");
+          CHECK(p >= 0 && p < L && slot >= base && slot < base + L + L / 16, "read slot");
           CHECK(stamp[slot] == epoch, "read of an unwritten slot L=%d s=%d p=%d", L, s + 1, p);
           v[t][reg(L, s + 1, k, q)] = lds[slot];
         }
   }
+}
+
+// LDS bank pairs of the exchanges of C interleaved lines (lane l of a wave:
+// column l mod C, thread l / C; C = 1: one line per wave): an 8-byte access
+// of a wave is modelled as four cycles of 16 lanes over 16 bank pairs (32
+// banks of 4 bytes), and a cycle whose lanes fall on the same pair at two
+// different slots is a conflict.  Returns the number of conflicting cycles.
+static int bank_conflicts(int L, int C, int pitch) {
+  const int TL = threads(L), NT = C * TL;
+  int bad = 0;
+  for (int s = 0; s + 1 < nstages(L); ++s)
+    for (int dir = 0; dir < 2; ++dir) {
+      const int R = radix(L, dir ? s + 1 : s), NB = 16 / R;
+      for (int k = 0; k < NB; ++k)
+        for (int q = 0; q < R; ++q)
+          for (int g0 = 0; g0 < NT; g0 += 16) {
+            int slot_of_pair[16];
+            for (int i = 0; i < 16; ++i) slot_of_pair[i] = -1;
+            bool conflict = false;
+            for (int tid = g0; tid < g0 + 16 && tid < NT; ++tid) {
+              const int c = tid % C, t = tid / C;
+              const int p = dir ? in_pos(L, s + 1, t + TL * k, q) : out_pos(L, s, t + TL * k, q);
+              const int slot = c * pitch + pad(p);
+              int& o = slot_of_pair[slot % 16];
+              if (o >= 0 && o != slot) conflict = true;
+              o = slot;
+            }
+            bad += conflict;
+          }
+    }
+  return bad;
 }
 
 int main(int argc, char** argv) {
@@ -83,10 +114,17 @@ int main(int argc, char** argv) {
   std::normal_distribution<double> nd(0.0, 1.0);
   std::vector<cd> x(n), mid(n), X(n, cd(NAN, NAN));
   for (auto& e : x) e = cd(nd(rng), nd(rng));
+  {
+    const int b0 = bank_conflicts(L0, C, line_pitch_c(L0, C)), b1 = bank_conflicts(L1, 1, line_pitch(L1));
+    if (b0 || b1) {
+      std::printf("LDS bank conflicts: first pass %d, last pass %d cycles\n", b0, b1);
+      return 1;
+    }
+  }
   // first pass: column blocks of C columns, results stored row-major [L0][L1]
   {
     const int TL = threads(L0);
-    std::vector<cd> lds((size_t)C * line_pitch(L0));
+    std::vector<cd> lds((size_t)C * line_pitch_c(L0, C));
     std::vector<int> stamp(lds.size(), 0);
     int epoch = 0;
     for (int sb = 0; sb < L1 / C; ++sb) {
@@ -95,7 +133,7 @@ int main(int argc, char** argv) {
         std::vector<std::vector<cd>> v(TL, std::vector<cd>(16));
         for (int t = 0; t < TL; ++t)
           for (int q = 0; q < 16; ++q) v[t][q] = x[(int64_t)(t + q * TL) * L1 + s0 + c];
-        run_line_stages(L0, TL, v, lds, stamp, c * line_pitch(L0), epoch);
+        run_line_stages(L0, TL, v, lds, stamp, c * line_pitch_c(L0, C), epoch);
         if (fails) return 1;
         for (int t = 0; t < TL; ++t)
           for (int r = 0; r < 16; ++r) {
