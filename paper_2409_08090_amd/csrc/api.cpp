@@ -1398,12 +1398,16 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
   off += al(sizeof(Work) * m);
   const size_t o_st = off;
   off += al(sizeof(int) * nstatus);
+  // each of a chunk's item lists starts on a 256-byte boundary with 256
+  // bytes to spare: the reservation adds up exactly what the upload below
+  // advances by, list by list
+  auto list_bytes = [&](size_t n) { return al(sizeof(BatchItem) * n) + 256; };
   std::vector<size_t> o_items(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     o_items[k] = off;
-    size_t cnt = ci[k].spread.size() + ci[k].last.size() + ci[k].small.size();
-    for (int ip = 0; ip < kMaxPass - 1; ++ip) cnt += ci[k].pass[ip].size();
-    off += al(sizeof(BatchItem) * cnt) + 256 * (kMaxPass + 2);
+    off += list_bytes(ci[k].spread.size()) + list_bytes(ci[k].last.size()) +
+           list_bytes(ci[k].small.size());
+    for (int ip = 0; ip < kMaxPass - 1; ++ip) off += list_bytes(ci[k].pass[ip].size());
   }
   const size_t dev_bytes = off + 256;
   if (ctx->budget && ctx->plan_bytes + ctx->ws_bytes + dev_bytes + ws_max > ctx->budget)
@@ -1488,7 +1492,7 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
       const BatchItem* ptr = reinterpret_cast<const BatchItem*>(B.dev + io);
       if (!v.empty() && he == hipSuccess)
         he = hipMemcpy(B.dev + io, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice);
-      io += al(sizeof(BatchItem) * v.size()) + 256;
+      io += list_bytes(v.size());
       return ptr;
     };
     L.spread_items = put(ci[k].spread);

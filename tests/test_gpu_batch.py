@@ -171,6 +171,32 @@ def test_onchip_and_staged_series_in_one_batch(precision):
         assert np.max(np.abs(p - q)) <= 2 * TOL[precision] * np.max(np.abs(q)), c.nd
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_mixed_batch_in_a_fresh_context(seed):
+    """Small and large series (some of the small ones run on chip) in the
+    first batch of a fresh context, whose descriptor buffer is then allocated
+    to the exact size the batch needs: every item list (spread, passes, last
+    pass, on-chip) of every chunk must stay inside its reservation.  (The
+    reservation once rounded the lists' total where the upload rounds each
+    list, and seed 1 ran past the buffer: 'batch descriptor upload: invalid
+    argument'.)  Each series against the oracle."""
+    rng = np.random.default_rng(100 + seed)
+    nds = [int(x) for x in rng.integers(30, 400, 1 + seed % 3)]
+    nds += [int(x) for x in rng.integers(2500, 6000, 1 + seed // 3)]
+    curves = [workloads.batch_curve(rng, nd) for nd in nds]
+    ctx = mils.Context(0)
+    try:
+        out, st = run_batch(curves, "fp64", ctx=ctx)
+    finally:
+        ctx.close()
+    assert np.all(st == 0)
+    krng = np.random.default_rng(2)
+    for c, p in zip(curves, out):
+        k = sample_k(c.nf, krng)
+        ref = oracle.periodogram(c.t, c.y, c.dy, c.f0, c.df, k=k)
+        assert np.max(np.abs(p[k] - ref)) <= TOL["fp64"] * np.max(np.abs(ref)), c.nd
+
+
 def test_tuning_cache_persists_decisions(tmp_path, monkeypatch):
     """With MILS_TUNE_CACHE naming a file, the autotuner's decisions are
     appended there and a new context for the same device reads them at
