@@ -147,8 +147,11 @@ def _check_fft2_plan(d, prec):
     assert L0 in (2048, 4096, 8192) and L1 in (2048, 4096), d
     C = d["first_cols"]
     assert C == min(8, 16384 // L0) and C * L0 // 16 <= 1024 and 3 * L1 // 16 <= 1024, d
-    lp = lambda L: L + L // 16 + (16 // C if C >= 2 else 8)  # noqa: E731
-    assert d["first_lds_bytes"] == C * lp(L0) * 8 + _tw2(L0) * elem + L0 <= 163840, d
+    # first-pass lines are 16/C elements apart modulo 16 (distinct LDS bank
+    # pairs for the lanes of one access cycle); last-pass lines pad by 8
+    lp_first = lambda L: L + L // 16 + (16 // C if C >= 2 else 8)  # noqa: E731
+    lp = lambda L: L + L // 16 + 8  # noqa: E731
+    assert d["first_lds_bytes"] == C * lp_first(L0) * 8 + _tw2(L0) * elem + L0 <= 163840, d
     if prec == "fp64":  # three grids side by side, exchanged and gathered in halves
         last = max(3 * lp(L1) * 8, 3 * (L1 // 2) * elem) + _tw2(L1) * elem
     else:  # the three grids one after another through one exchange line
