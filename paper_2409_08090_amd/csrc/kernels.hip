@@ -151,36 +151,60 @@ __global__ __launch_bounds__(kThreads) void k_stats_final(CallArgs a, Work w, in
 // reads them) whose cell lies in bin b or later; bin_start[nbins] = nd.
 // ============================================================================
 // Sorted fast path: when the bins of consecutive points are non-decreasing,
-// bin_start[b] is the first point whose bin is >= b, found by a binary search
-// per bin (every bin costs the same, whatever the gaps in the data).  Each
-// point also checks its predecessor; a descent sets need_sort and the
-// counting sort below rebuilds everything.
+// bin_start[b] is the first point whose bin is >= b.  The bins up to the
+// first point's all start at point 0 and those after the last point's at nd:
+// the whole grid writes them (they can be most of the grid: the frequency
+// step makes the grid's period several times the time span).  Every other
+// point j starts the bins (bin(j-1), bin(j)], so it computes its own and its
+// predecessor's bin and writes those entries: each bin is written by exactly
+// one point, and a run longer than 8 bins (a gap in the data) by the whole
+// wave.  A descent sets need_sort instead, and the counting sort below
+// rebuilds everything.
 __global__ __launch_bounds__(kThreads) void k_bins_sorted(CallArgs a, Plan p, Work w) {
   const DevStats* st = w.stats;
   if (st->status != 0) return;
   if (a.wstats && !st->need_sort) return;  // the weights-only call's bins hold
   const int nd = (int)a.nd;
   const int nb = (int)p.nbins;
+  const int64_t gtid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
   // The histogram of the counting sort is cleared by every block, before any
   // early exit: need_sort may be raised by another block of this launch.
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i <= nb;
-       i += (int64_t)gridDim.x * kThreads)
-    w.bin_count[i] = 0;
+  for (int64_t i = gtid; i <= nb; i += stride) w.bin_count[i] = 0;
   if (st->need_sort) return;
   const double tau = st->tau;
-  const int64_t total = nd > nb + 1 ? nd : nb + 1;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * kThreads) {
-    if (i >= 1 && i < nd) {
-      const int kp = point_bin(a.t[i - 1], tau, a.df, p);
-      const int kc = point_bin(a.t[i], tau, a.df, p);
-      if (kc < kp) atomicOr(&w.stats->need_sort, 1);
+  const int b_first = point_bin(a.t[0], tau, a.df, p);
+  const int b_last = point_bin(a.t[nd - 1], tau, a.df, p);
+  for (int64_t b = gtid; b <= nb; b += stride) {
+    if (b <= b_first) w.bin_start[b] = 0;
+    else if (b > b_last) w.bin_start[b] = nd;
+  }
+  const int lane = threadIdx.x & 63;
+  // wave-uniform loop over points 1 .. nd-1: every lane takes part in the
+  // ballot and the shuffles
+  for (int64_t j0 = 1 + (int64_t)blockIdx.x * kThreads + (threadIdx.x - lane); j0 < nd;
+       j0 += stride) {
+    const int64_t j = j0 + lane;
+    int lo = 0, hi = -1;  // the bins [lo, hi] that start at point j
+    if (j < nd) {
+      const int bp = point_bin(a.t[j - 1], tau, a.df, p);
+      const int bc = point_bin(a.t[j], tau, a.df, p);
+      if (bc < bp) atomicOr(&w.stats->need_sort, 1);
+      else {
+        lo = bp + 1;
+        hi = bc;
+      }
     }
-    if (i <= nb) {
-      const int b = (int)i;
-      // first j in [0, nd) with bin(j) >= b, else nd
-      w.bin_start[b] =
-          lower_bound_idx(nd, b, [&](int j) { return point_bin(a.t[j], tau, a.df, p); });
+    const bool run = hi - lo >= 8;
+    if (!run)
+      for (int b = lo; b <= hi; ++b) w.bin_start[b] = (int)j;
+    unsigned long long runs = __ballot(run);
+    while (runs) {
+      const int src = __ffsll(runs) - 1;
+      runs &= runs - 1;
+      const int l = __shfl(lo, src, 64), h = __shfl(hi, src, 64);
+      const int v = (int)(j0 + src);
+      for (int b = l + lane; b <= h; b += 64) w.bin_start[b] = v;
     }
   }
 }
