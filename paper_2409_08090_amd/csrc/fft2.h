@@ -136,12 +136,12 @@ struct Fft2Bufs {
   const unsigned char* rowflag[3];  // active rows of each grid's geometry
 };
 
-// LDS bytes of a first-pass workgroup: the exchange lines, the twiddle table
-// of L0 and the row flags.
+// LDS bytes of a first-pass workgroup: the exchange lines and the twiddle
+// table of L0.
 template <typename Real>
 __host__ __device__ constexpr size_t f2_first_lds(int L0, int C, bool halves) {
   return (size_t)C * fft2::line_pitch_c(L0, C) * (halves ? sizeof(Real) : 2 * sizeof(Real)) +
-         (size_t)tw2_count(L0) * 2 * sizeof(Real) + (size_t)L0;
+         (size_t)tw2_count(L0) * 2 * sizeof(Real);
 }
 // LDS bytes of a last-pass workgroup: the exchange lines (reused for the
 // grids' results) and the twiddle table of L1.

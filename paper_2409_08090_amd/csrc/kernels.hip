@@ -641,20 +641,25 @@ __global__ __launch_bounds__(C * L0 / 16, 4) void k_fft2_first(Fft2Bufs<Real> b,
   const int64_t s = sb * C + c;
   Lds* ex = reinterpret_cast<Lds*>(smem);
   T2* twl = reinterpret_cast<T2*>(smem + (size_t)C * LP * sizeof(Lds));
-  unsigned char* rf = reinterpret_cast<unsigned char*>(twl + tw2_count(L0));
-  // row flags (and the twiddle table) first: the loads depend on them
-  for (int x = tid; x < tw2_count(L0); x += NT) twl[x] = tw[ps.twL_off + x];
+  // the flags of this thread's 16 rows straight from memory (every workgroup
+  // of the grid reads the same L0 bytes, so they come from the cache), then
+  // the rows' loads, and only then the twiddle table into LDS: staging the
+  // flags in LDS put a barrier before every workgroup's first load (first
+  // pass 317 -> 305 us FP64, 202 -> 187 us FP32 at 4096 x 4096)
   const unsigned char* rfg = b.rowflag[g];
-  for (int x = tid; x < L0; x += NT) rf[x] = rfg[x];
-  __syncthreads();
+  unsigned char fl[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) fl[q] = rfg[t + q * TL];
   T2 v[16];
   const T2* in = b.grid[g] + s;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int row = t + q * TL;
     v[q] = czero<T2>();
-    if (rf[row]) v[q] = in[(int64_t)row * L1];
+    if (fl[q]) v[q] = in[(int64_t)row * L1];
   }
+  for (int x = tid; x < tw2_count(L0); x += NT) twl[x] = tw[ps.twL_off + x];
+  __syncthreads();
   // inter-pass twiddles exp(2 pi i s m0 / n) of this thread's outputs
   // m0 = t + TL j: the first and the step from the two-level table, fetched
   // before the transform so that their latency overlaps it

@@ -139,8 +139,8 @@ def _check_fft2_plan(d, prec):
     # two-pass register-tile plans: lines of 2048..8192 (three grids: last
     # line at most 4096), workgroups of at most 1024 threads (16 elements
     # each), LDS of the exchange lines (one half at a time in FP64: 8 bytes
-    # per element), the two-level twiddle table and (first pass) the row
-    # flags, or (last pass) the other grids' results, within 160 KB
+    # per element), the two-level twiddle table and (last pass) the other
+    # grids' results, within 160 KB
     elem = 16 if prec == "fp64" else 8
     L0, L1 = d["len"]
     assert d["npass"] == 2 and d["n"] == L0 * L1, d
@@ -151,7 +151,7 @@ def _check_fft2_plan(d, prec):
     # pairs for the lanes of one access cycle); last-pass lines pad by 8
     lp_first = lambda L: L + L // 16 + (16 // C if C >= 2 else 8)  # noqa: E731
     lp = lambda L: L + L // 16 + 8  # noqa: E731
-    assert d["first_lds_bytes"] == C * lp_first(L0) * 8 + _tw2(L0) * elem + L0 <= 163840, d
+    assert d["first_lds_bytes"] == C * lp_first(L0) * 8 + _tw2(L0) * elem <= 163840, d
     if prec == "fp64":  # three grids side by side, exchanged and gathered in halves
         last = max(3 * lp(L1) * 8, 3 * (L1 // 2) * elem) + _tw2(L1) * elem
     else:  # the three grids one after another through one exchange line
