@@ -456,8 +456,12 @@ int ensure_workspace(mils_context* ctx, size_t bytes) {
   ctx->ws = p;
   ctx->ws_bytes = got;
   mils_log(2, "workspace grown to %.1f MB", (double)got / 1e6);
-  // the statistics block holds the self-resetting reduction counter
+  // the statistics block holds the self-resetting reduction counter.  The
+  // memset runs on the null stream and may still be in flight when
+  // hipMemset returns; a caller's non-blocking stream (a server lane's) is
+  // not ordered after it, so wait for it here.
   hipError_t he = hipMemset(p, 0, 4096);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) return hip_fail(ctx, he, "workspace init");
   return MILS_OK;
 }
@@ -1456,15 +1460,18 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
       woff += wsz[c];
     }
   }
-  he = hipMemcpy(B.dev + o_cur, cur.data(), sizeof(BatchCurve) * m, hipMemcpyHostToDevice);
-  if (he == hipSuccess)
-    he = hipMemcpy(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls, hipMemcpyHostToDevice);
-  if (he == hipSuccess)
-    he = hipMemcpy(B.dev + o_tw, twp.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
-  if (he == hipSuccess)
-    he = hipMemcpy(B.dev + o_ph, php.data(), sizeof(void*) * ncls, hipMemcpyHostToDevice);
-  if (he == hipSuccess)
-    he = hipMemcpy(B.dev + o_work, works.data(), sizeof(Work) * m, hipMemcpyHostToDevice);
+  // descriptor uploads on the call's stream (then waited for below): the
+  // batch's kernels follow on that stream, which may be a non-blocking one
+  // that copies on the null stream would not precede
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (he == hipSuccess && bytes)
+      he = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  up(B.dev + o_cur, cur.data(), sizeof(BatchCurve) * m);
+  up(B.dev + o_plan, plans.data(), sizeof(Plan) * ncls);
+  up(B.dev + o_tw, twp.data(), sizeof(void*) * ncls);
+  up(B.dev + o_ph, php.data(), sizeof(void*) * ncls);
+  up(B.dev + o_work, works.data(), sizeof(Work) * m);
   B.launches.assign(nchunks, BatchLaunch{});
   ctx->last_batch_onchip = 0;
   for (int k = 0; k < nchunks && he == hipSuccess; ++k) {
@@ -1490,8 +1497,7 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     size_t io = o_items[k];
     auto put = [&](const std::vector<BatchItem>& v) -> const BatchItem* {
       const BatchItem* ptr = reinterpret_cast<const BatchItem*>(B.dev + io);
-      if (!v.empty() && he == hipSuccess)
-        he = hipMemcpy(B.dev + io, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice);
+      up(B.dev + io, v.data(), sizeof(BatchItem) * v.size());
       io += list_bytes(v.size());
       return ptr;
     };
@@ -1510,6 +1516,8 @@ int build_batch(mils_context* ctx, BatchState& B, const std::vector<int64_t>& id
     L.small_lds = ci[k].small_lds;
     ctx->last_batch_onchip += L.nsmall;
   }
+  // the host vectors are released on return
+  if (he == hipSuccess) he = hipStreamSynchronize(stream);
   if (he != hipSuccess) return hip_fail(ctx, he, "batch descriptor upload");
   B.status_dev = reinterpret_cast<int*>(B.dev + o_st);
   if (B.exec) (void)hipGraphExecDestroy(B.exec);

@@ -733,8 +733,10 @@ __global__ __launch_bounds__(G * L1 / 16, G == 3 ? 3 : 2) void k_fft2_last(Fft2B
                    : 0.0;
     }
   }
+  // no barrier here: the first stage uses no table twiddles, and the first
+  // exchange's barrier orders these stores before the second stage reads
+  // them (last pass 302 -> 295 us in FP64)
   for (int x = tid; x < tw2_count(L1); x += NT) twl[x] = tw[ps.twL_off + x];
-  __syncthreads();
   f2_line<L1, HALVES>(v, t, ex + g * LP, twl);
   const int64_t n = pl.n, nf = a.nf, K = pl.K;
   if constexpr (G == 3) {
