@@ -456,10 +456,12 @@ int ensure_workspace(mils_context* ctx, size_t bytes) {
   ctx->ws = p;
   ctx->ws_bytes = got;
   mils_log(2, "workspace grown to %.1f MB", (double)got / 1e6);
-  // the statistics block holds the self-resetting reduction counter.  The
-  // memset runs on the null stream and may still be in flight when
-  // hipMemset returns; a caller's non-blocking stream (a server lane's) is
-  // not ordered after it, so wait for it here.
+  // the statistics block starts cleared (every call's statistics kernels
+  // rewrite it before any other kernel reads it).  The memset runs on the
+  // null stream and may still be in flight when hipMemset returns; a
+  // caller's non-blocking stream (a server lane's) is not ordered after it,
+  // so wait for it here: it once landed in the middle of a lane's first
+  // call.
   hipError_t he = hipMemset(p, 0, 4096);
   if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he != hipSuccess) return hip_fail(ctx, he, "workspace init");
